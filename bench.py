@@ -1,0 +1,194 @@
+"""Benchmark: ADM1 particle-steps per second of the per-particle reaction step.
+
+Workload (default): the batched population of 2^20 particles (per-particle
+temperature 30-40 C with Arrhenius-scaled rates, a 5 % feed zone pulsed with
+10x substrate on even coupling steps), 10 coupling steps of dt = 1/96 d,
+FP64 integrator at rtol 1e-8.  One timed step = one coupling interval of the
+whole hot path: the adaptive Rosenbrock step of every particle
+(adm1_step_particles) and the tank gas flows (adm1_gas_flux).  Inputs are in
+HBM before the timed region.  Warm-up steps run on a copy of the initial
+state, which is restored before timing, so the timed steps are the
+workload's first K coupling intervals.
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12  # MI355X FP64 vector, FLOP/s
+PEAK_HBM = 8.0e12    # bytes/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--cpu-sample", type=int, default=1024,
+                    help="particles of the oracle CPU-baseline sample (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, rtol, n_sample, steps):
+    """The oracle, as it stands, on a stratified sample of the same workload."""
+    from oracle.adm1 import Oracle
+    from paper_2311_08927_amd import workloads as W
+    rng = np.random.default_rng(123)
+    zone = np.flatnonzero(w.zone)
+    other = np.flatnonzero(~w.zone)
+    nz = max(1, int(round(n_sample * len(zone) / w.n)))
+    idx = np.sort(np.concatenate([rng.choice(zone, nz, replace=False),
+                                  rng.choice(other, n_sample - nz, replace=False)]))
+    sub = W.subset(w, idx)
+    orc = Oracle(W.params_path(), rtol=rtol, atol=W.atol_vector(rtol))
+    cores = len(os.sched_getaffinity(0))
+    X = sub.X.copy()
+    H = np.full(sub.ld, -1.0)
+    hl = np.full(sub.ld, -1.0)
+    t0 = time.perf_counter()
+    for s in range(steps):
+        orc.step(X, sub.T, sub.D_at(s), sub.fidx, sub.feed, sub.dt, H=H, hlast=hl, n=sub.n,
+                 nthreads=cores)
+    el = time.perf_counter() - t0
+    return {"value": sub.n * steps / el, "unit": "particle-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{sub.n} particles ({nz} in the feed zone) x {steps} coupling steps "
+                      f"of the same workload, std::thread-style equal chunks, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "particle step shards by index range with no exchange besides four gas "
+              "totals, so N GPUs would each run this single-GPU path on n/N particles.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2311_08927_amd import adm1 as A
+    from paper_2311_08927_amd import flops as F
+    from paper_2311_08927_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = W.batched_population(args.n, seed=2, steps=args.steps)
+    ctx = A.Context(w.ld, rtol=args.rtol, atol=W.atol_vector(args.rtol), variant=args.variant)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    X0 = t(w.X)
+    X = X0.clone()
+    T = t(w.T)
+    D_even, D_odd = t(w.D_at(0)), t(w.D_at(1))
+    fidx, S_in = t(w.fidx), t(w.feed)
+    H = torch.full((w.n,), -1.0, dtype=torch.float64, device=dev)
+    hl = torch.full((w.n,), -1.0, dtype=torch.float64, device=dev)
+    status = torch.zeros(w.n, dtype=torch.uint8, device=dev)
+    K = args.steps
+    nsteps = torch.zeros((K, 3, w.ld), dtype=torch.int32, device=dev)
+    V_liq = torch.full((w.n,), 3400.0, dtype=torch.float64, device=dev)
+    q_gas = torch.empty(w.n, dtype=torch.float64, device=dev)
+    q_ch4 = torch.empty(w.n, dtype=torch.float64, device=dev)
+    totals = torch.empty((K, 4), dtype=torch.float64, device=dev)
+    feeds = [A.feed_struct(D_even, fidx, S_in), A.feed_struct(D_odd, fidx, S_in)]
+    aux = A.adm1_aux(H.data_ptr(), hl.data_ptr())
+    stream = torch.cuda.current_stream()
+
+    def one_step(k, ns, tot):
+        A.adm1_step_particles(ctx.handle, X, w.ld, T, feeds[k % 2], w.dt, w.n, aux, status, ns,
+                              stream)
+
+    def gas(k, tot):
+        A.adm1_gas_flux(ctx.handle, X, w.ld, T, V_liq, w.n, q_gas, q_ch4, tot, stream)
+
+    # warm-up on a copy, then restore the initial state and warm starts
+    for k in range(args.warmup):
+        one_step(k, nsteps[0], totals[0])
+        gas(k, totals[0])
+    torch.cuda.synchronize()
+    X.copy_(X0)
+    H.fill_(-1.0)
+    hl.fill_(-1.0)
+    nsteps.zero_()
+    torch.cuda.synchronize()
+
+    ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for k in range(K):
+        ev_s[k].record(stream)
+        one_step(k, nsteps[k], totals[k])
+        ev_e[k].record(stream)
+        gas(k, totals[k])
+        print(f"# step {k} enqueued", file=sys.stderr, flush=True)
+    end.record(stream)
+    end.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(end)
+    step_ms = [ev_s[k].elapsed_time(ev_e[k]) for k in range(K)]
+
+    st = status.cpu().numpy()
+    ns = nsteps.cpu().numpy().astype(np.int64)
+    acc = int(ns[:, 0, :w.n].sum())
+    rej = int(ns[:, 1, :w.n].sum())
+    newt = int(ns[:, 2, :w.n].sum())
+    flop = F.total_flops(acc + rej, newt, w.n * K)
+    kern_s = sum(step_ms) / 1e3
+    achieved = flop / kern_s
+    value = w.n * K / (total_ms / 1e3)
+    out = {
+        "metric": "ADM1 particle-steps/sec (FP64 integrator vs gated surrogate) at stated error",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched ADM1 population: 2^20 particles, T U(30,40) C, 5% "
+                               "pulsed feed zone, 10 coupling steps of 1/96 d, rtol 1e-8"
+                   if args.n == 1 << 20 else f"batched ADM1 population, n={args.n}",
+                   "particles": w.n, "coupling_steps": K, "dt_days": w.dt, "rtol": args.rtol,
+                   "path": "fp64 integrator", "variant": args.variant},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "kernel": "adm1 step (k_step*)",
+                     "avg_launch_ms": sum(step_ms) / K,
+                     "flops_per_launch": flop / K},
+        "detail": {"accepted_steps": acc, "rejected_steps": rej, "newton_iters": newt,
+                   "attempts_per_particle_step": (acc + rej) / (w.n * K),
+                   "status_counts": np.bincount(st & 0x7F, minlength=5).tolist(),
+                   "hbm_bytes_per_particle_step": F.BYTES_PER_PARTICLE_STEP,
+                   "hbm_frac": w.n * F.BYTES_PER_PARTICLE_STEP / (sum(step_ms) / K / 1e3)
+                   / PEAK_HBM,
+                   "step_ms": step_ms, "wall_s": wall},
+    }
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = cpu_baseline(w, args.rtol, args.cpu_sample, args.cpu_steps)
+        out["detail"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

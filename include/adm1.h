@@ -1,0 +1,213 @@
+/*
+ * adm1.h -- C ABI of the MI355X per-particle ADM1 reaction step.
+ *
+ * The problem (Kumar et al., "Introducing CHAD", arXiv 2311.08927, sec. 2.3):
+ * N independent particles, each a CSTR with its own ADM1 state, temperature
+ * and feed, are advanced over one synchronised coupling interval dt.  The
+ * state obeys the mass balance of eq. 2 with the standard ADM1 rates
+ * (sec. 2.2) and inhibition forms (eqs. 3-6); S_H+ and S_h2 are algebraic,
+ * fixed by the charge balance (eq. 7) and the hydrogen balance (eq. 8).
+ *
+ * Conventions common to every call
+ *   - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA
+ *     tensors) unless stated otherwise; the caller owns them.  The library
+ *     owns only the context and its scratch buffers.
+ *   - `state` is float64 structure-of-arrays [35][ld]: entry k of particle i
+ *     is state[k*ld + i]; ld >= n and ld % 64 == 0.  Entries (units kg COD/m3
+ *     unless noted): 0 S_su, 1 S_aa, 2 S_fa, 3 S_va, 4 S_bu, 5 S_pro, 6 S_ac,
+ *     7 S_h2, 8 S_ch4, 9 S_IC (kmol C/m3), 10 S_IN (kmol N/m3), 11 S_I,
+ *     12 X_xc, 13 X_ch, 14 X_pr, 15 X_li, 16 X_su, 17 X_aa, 18 X_fa, 19 X_c4,
+ *     20 X_pro, 21 X_ac, 22 X_h2, 23 X_I, 24 S_cat (kmol/m3), 25 S_an
+ *     (kmol/m3), 26 S_va-, 27 S_bu-, 28 S_pro-, 29 S_ac-, 30 S_hco3- (kmol/m3),
+ *     31 S_nh3 (kmol/m3), 32 G_h2, 33 G_ch4, 34 G_co2 (kmol/m3).
+ *     Entries 7 and 26..31 are algebraic: on input only entry 7 is read (as a
+ *     starting guess for eq. 8); on output all seven hold the values
+ *     consistent with the final differential entries.
+ *   - Time in days, temperature in K, dilution rates in 1/d, flows in m3/d.
+ *   - `stream` is a hipStream_t (NULL: the default stream).  Calls only
+ *     enqueue work: they neither allocate nor synchronise, so they may be
+ *     captured into a hipGraph.  Exceptions are marked "synchronous".
+ *   - Return value: 0 on success; a negative ADM1_E* code for an invalid
+ *     argument (nothing is enqueued); a positive value is a HIP error code
+ *     from a launch.  adm1_strerror() names them.
+ *   - Per-particle outcomes go to `status` (uint8 per particle):
+ *       0 ok, 1 algebraic solve failed at the interval start, 2 step size
+ *       underflow, 3 max_steps reached, 4 non-finite input; bit 0x80 set
+ *       (with code 0) when a differential entry ended negative.
+ *     A particle with a nonzero code keeps its input state and warm starts.
+ */
+#ifndef ADM1_H
+#define ADM1_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ADM1_OK = 0,
+    ADM1_E_NULL = -1,        /* a required pointer is NULL */
+    ADM1_E_SIZE = -2,        /* n < 0, n > n_max, ld < n or ld % 64 != 0 */
+    ADM1_E_NOT_DEVICE = -3,  /* a pointer that must be device memory is not */
+    ADM1_E_PARAMS = -4,      /* parameter set fails COD/C/N continuity or range */
+    ADM1_E_OPTS = -5,        /* invalid integration options */
+    ADM1_E_FEED = -6,        /* feed table invalid (n_feed < 1) */
+    ADM1_E_NOMEM = -7,       /* context scratch allocation failed (adm1_init) */
+    ADM1_E_VARIANT = -8,     /* unknown kernel variant */
+    ADM1_E_DT = -9           /* dt not positive and finite */
+};
+
+/* Status codes written per particle. */
+enum {
+    ADM1_ST_OK = 0, ADM1_ST_ALGEBRAIC = 1, ADM1_ST_UNDERFLOW = 2, ADM1_ST_MAXSTEPS = 3,
+    ADM1_ST_NONFINITE = 4, ADM1_ST_NEGATIVE = 0x80
+};
+
+/* ADM1 parameters (sec. 2.2; values of the standard ADM1 set).  Host struct.
+ * Stoichiometric fractions f_*, yields Y_*, carbon contents C_* (kmol C per
+ * kg COD) and nitrogen contents N_* (kmol N per kg COD); kinetic constants at
+ * T_ref_kin (1/d, kg COD/m3); pH limits of the Hill inhibitions (eqs. 3-4);
+ * van't Hoff base values at T_base with enthalpies dH_* (J/mol); the gas
+ * phase: k_L_a (1/d), headspace valve k_p per m3 liquid (m3/(d bar m3)),
+ * V_gas/V_liq, P_atm (bar).  E_a (J/mol) sets the Arrhenius factor
+ * exp(E_a/(100 R) (1/T_ref_kin - 1/T)) on k_dis, k_hyd, k_m and k_dec.  The
+ * field order is also returned by adm1_param_names(). */
+typedef struct adm1_params {
+    double f_sI_xc, f_xI_xc, f_ch_xc, f_pr_xc, f_li_xc;
+    double N_xc, N_I, N_aa, N_bac;
+    double C_xc, C_sI, C_ch, C_pr, C_li, C_xI, C_su, C_aa, C_fa, C_va, C_bu, C_pro, C_ac,
+        C_bac, C_ch4;
+    double f_fa_li, f_h2_su, f_bu_su, f_pro_su, f_ac_su;
+    double f_h2_aa, f_va_aa, f_bu_aa, f_pro_aa, f_ac_aa;
+    double f_ac_fa, f_h2_fa, f_pro_va, f_ac_va, f_h2_va, f_ac_bu, f_h2_bu, f_ac_pro, f_h2_pro;
+    double Y_su, Y_aa, Y_fa, Y_c4, Y_pro, Y_ac, Y_h2;
+    double k_dis, k_hyd_ch, k_hyd_pr, k_hyd_li;
+    double k_m_su, K_S_su, k_m_aa, K_S_aa, k_m_fa, K_S_fa, K_I_h2_fa;
+    double k_m_c4, K_S_c4, K_I_h2_c4, k_m_pro, K_S_pro, K_I_h2_pro;
+    double k_m_ac, K_S_ac, K_I_nh3, k_m_h2, K_S_h2;
+    double k_dec_su, k_dec_aa, k_dec_fa, k_dec_c4, k_dec_pro, k_dec_ac, k_dec_h2;
+    double K_S_IN;
+    double pH_UL_aa, pH_LL_aa, pH_UL_ac, pH_LL_ac, pH_UL_h2, pH_LL_h2;
+    double eps_c4, E_a, T_ref_kin;
+    double R, T_base, K_w_base, dH_w;
+    double K_a_va, K_a_bu, K_a_pro, K_a_ac;
+    double K_a_co2_base, dH_a_co2, K_a_IN_base, dH_a_IN;
+    double K_H_h2_base, dH_H_h2, K_H_ch4_base, dH_H_ch4, K_H_co2_base, dH_H_co2;
+    double p_h2o_base, p_h2o_coef;
+    double k_L_a, k_p_per_V_liq, V_gas_per_V_liq, P_atm;
+} adm1_params;
+
+/* Integration options.  Host struct.
+ *   rtol, atol[28]: error control of the adaptive Rosenbrock integrator
+ *     (scaled RMS norm, sc_i = atol_i + rtol max(|y0_i|, |y1_i|)) over the 28
+ *     differential entries in integration order (state entries 0-6, 8-25,
+ *     32-34).
+ *   max_steps: attempted steps per particle per call (> 0).
+ *   newton_tol, newton_maxit: relative step tolerance and iteration cap of
+ *     the eq. 7 / eq. 8 Newton solves.
+ *   rate_precision: 0 rates and eq. 2 assembly in FP64; 1 in FP32 (the eq. 7
+ *     and eq. 8 solves and the linear algebra stay FP64).
+ *   variant: step-kernel layout; -1 lets the library choose (the autotuned
+ *     choice, see adm1_autotune); otherwise an ADM1_VARIANT_* value. */
+typedef struct adm1_opts {
+    double rtol;
+    double atol[28];
+    int32_t max_steps;
+    double newton_tol;
+    int32_t newton_maxit;
+    int32_t rate_precision;
+    int32_t variant;
+} adm1_opts;
+
+enum {
+    ADM1_VARIANT_DENSE1 = 0,  /* one lane per particle, dense bordered LU, pivoting */
+    ADM1_VARIANT_SPARSE1 = 1, /* one lane per particle, static-order sparse LU */
+    ADM1_VARIANT_SPARSE2 = 2, /* two lanes per particle, register-resident sparse LU */
+    ADM1_VARIANT_COUNT = 3
+};
+
+/* Feed description (device pointers).  D[i]: dilution rate q/V of particle i
+ * (1/d, 0 = closed particle); idx[i]: row of S_in giving its inflow
+ * concentrations; S_in: float64 [n_feed][26], inflow of state entries 0..25
+ * (entry 7 is the S_h2 inflow of eq. 8). */
+typedef struct adm1_feed {
+    const double *D;
+    const int32_t *idx;
+    const double *S_in;
+    int64_t n_feed;
+} adm1_feed;
+
+/* Warm starts carried from one coupling interval to the next (device
+ * pointers, length >= n): H[i] = S_H+ (kmol/m3), h_last[i] = the step size
+ * proposed at the end of the previous interval (d).  Entries <= 0 mean cold
+ * start (S_H+ from 1e-7, the first step from the Hairer-Norsett-Wanner
+ * starting-step estimate).  The step updates them for successful particles. */
+typedef struct adm1_aux {
+    double *H;
+    double *h_last;
+} adm1_aux;
+
+typedef struct adm1_ctx adm1_ctx;
+
+/* Create a context for up to n_max particles on the current HIP device.
+ * Derives the stoichiometric closures (inorganic C and N rows of the Petersen
+ * matrix of eq. 2) and checks COD continuity of every process; copies the
+ * parameters into the context.  Allocates the context scratch (work-queue
+ * counters and reduction buffers).  Synchronous.  *out is set on success. */
+int adm1_init(const adm1_params *p, const adm1_opts *o, int64_t n_max, adm1_ctx **out);
+
+/* Replace the integration options (host struct) of a context.  Synchronous. */
+int adm1_set_opts(adm1_ctx *ctx, const adm1_opts *o);
+
+/* Advance particles 0..n-1 by dt_days IN PLACE (the per-particle ADM1 step
+ * over one coupling interval, sec. 2.3).  state: [35][ld]; temp_K: [n];
+ * feed: see adm1_feed (host struct holding device pointers); aux: warm starts
+ * (host struct of device pointers, nullable: cold start for every particle);
+ * status: [n] uint8; nsteps (nullable): int32 [3][ld] = accepted steps,
+ * rejected steps, algebraic Newton iterations of each particle. */
+int adm1_step_particles(adm1_ctx *ctx, double *state, int64_t ld, const double *temp_K,
+                        const adm1_feed *feed, double dt_days, int64_t n, adm1_aux *aux,
+                        uint8_t *status, int32_t *nsteps, void *stream);
+
+/* Headspace gas flows (sec. 1: release of gaseous components) of particles
+ * 0..n-1: q_gas = V_liq k_p max(0, P_gas - P_atm) P_gas / P_atm and
+ * q_ch4 = q_gas p_ch4 / P_gas (m3/d), with P_gas the sum of the partial
+ * pressures and the water vapour pressure.  V_liq: [n] liquid volume of each
+ * particle (m3; NULL = 1 m3).  q_gas, q_ch4: [n] outputs (nullable).
+ * totals: [4] device output (q_gas, q_h2, q_ch4, q_co2 summed over the
+ * particles) reduced in a fixed order, so bit-identical run to run. */
+int adm1_gas_flux(adm1_ctx *ctx, const double *state, int64_t ld, const double *temp_K,
+                  const double *V_liq, int64_t n, double *q_gas, double *q_ch4,
+                  double *totals, void *stream);
+
+/* Right-hand side of eq. 2 (and the gas balances) for the 28 differential
+ * entries, with S_H+ and S_h2 solved from eqs. 7-8 at the given state.
+ * dxdt: float64 [28][ld_out] in integration order; H_out (nullable): [n]
+ * S_H+; rate_precision as in adm1_opts.  Status (nullable) gets 1 where an
+ * algebraic solve failed. */
+int adm1_rhs(adm1_ctx *ctx, const double *state, int64_t ld, const double *temp_K,
+             const adm1_feed *feed, int64_t n, double *dxdt, int64_t ld_out, double *H_out,
+             int32_t rate_precision, uint8_t *status, void *stream);
+
+/* Total Jacobian df/dy of the 28 differential entries (the algebraic
+ * unknowns eliminated through eqs. 7-8): float64 [n][28][28] row-major, for
+ * tests.  Status (nullable) as in adm1_rhs. */
+int adm1_jacobian(adm1_ctx *ctx, const double *state, int64_t ld, const double *temp_K,
+                  const adm1_feed *feed, int64_t n, double *J, uint8_t *status,
+                  void *stream);
+
+/* Comma-separated adm1_params field names in struct order (static string). */
+const char *adm1_param_names(void);
+
+/* Human-readable name of an ADM1_E* or HIP error code (static string). */
+const char *adm1_strerror(int code);
+
+/* Free the context and its scratch.  Synchronous.  NULL is a no-op. */
+void adm1_destroy(adm1_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADM1_H */

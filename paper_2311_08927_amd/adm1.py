@@ -1,0 +1,264 @@
+"""Thin ctypes binding of libadm1.so (the C ABI in include/adm1.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels.  Functions carry the C names; tensors are torch CUDA tensors whose
+data pointers are passed through, streams are torch streams (default: the
+current stream).  If the library is missing, the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libadm1.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "adm1.h")
+NX, ND, NLIQ = 35, 28, 26
+
+VARIANT_DENSE1, VARIANT_SPARSE1, VARIANT_SPARSE2 = 0, 1, 2
+ERRORS = {0: "ok", -1: "E_NULL", -2: "E_SIZE", -3: "E_NOT_DEVICE", -4: "E_PARAMS",
+          -5: "E_OPTS", -6: "E_FEED", -7: "E_NOMEM", -8: "E_VARIANT", -9: "E_DT"}
+
+_lib = None
+
+
+class ADM1Error(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {code} ({strerror(code)})")
+
+
+class adm1_opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double * ND),
+                ("max_steps", ctypes.c_int32), ("newton_tol", ctypes.c_double),
+                ("newton_maxit", ctypes.c_int32), ("rate_precision", ctypes.c_int32),
+                ("variant", ctypes.c_int32)]
+
+
+class adm1_feed(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_void_p), ("idx", ctypes.c_void_p), ("S_in", ctypes.c_void_p),
+                ("n_feed", ctypes.c_int64)]
+
+
+class adm1_aux(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_void_p), ("h_last", ctypes.c_void_p)]
+
+
+def lib():
+    """Load libadm1.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: the HIP extension is not built "
+                               "(run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.adm1_param_names.restype = ctypes.c_char_p
+        L.adm1_strerror.restype = ctypes.c_char_p
+        L.adm1_strerror.argtypes = [ctypes.c_int]
+        L.adm1_init.restype = ctypes.c_int
+        L.adm1_init.argtypes = [vp, vp, i64, ctypes.POINTER(vp)]
+        L.adm1_set_opts.restype = ctypes.c_int
+        L.adm1_set_opts.argtypes = [vp, vp]
+        L.adm1_destroy.argtypes = [vp]
+        L.adm1_step_particles.restype = ctypes.c_int
+        L.adm1_step_particles.argtypes = [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp]
+        L.adm1_gas_flux.restype = ctypes.c_int
+        L.adm1_gas_flux.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, vp, vp]
+        L.adm1_rhs.restype = ctypes.c_int
+        L.adm1_rhs.argtypes = [vp, vp, i64, vp, vp, i64, vp, i64, vp, i32, vp, vp]
+        L.adm1_jacobian.restype = ctypes.c_int
+        L.adm1_jacobian.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().adm1_strerror(int(code)).decode()
+
+
+def param_names() -> list[str]:
+    return lib().adm1_param_names().decode().split(",")[:-1]
+
+
+def load_params(path: str | None = None) -> dict:
+    path = path or os.path.join(PKG, "data", "adm1_params.json")
+    with open(path) as fh:
+        return json.load(fh)["values"]
+
+
+def make_params(values: dict):
+    names = param_names()
+    arr = (ctypes.c_double * len(names))(*[float(values[n]) for n in names])
+    return arr
+
+
+def make_opts(rtol=1e-8, atol=None, max_steps=100000, newton_tol=1e-14, newton_maxit=100,
+              rate_precision=0, variant=-1) -> adm1_opts:
+    if atol is None:
+        atol = np.full(ND, 1e-12)
+    atol = np.asarray(atol, dtype=np.float64)
+    assert atol.shape == (ND,)
+    return adm1_opts(rtol, (ctypes.c_double * ND)(*atol), max_steps, newton_tol, newton_maxit,
+                     rate_precision, variant)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ADM1Error(rc, what)
+
+
+def feed_struct(D, idx, S_in) -> adm1_feed:
+    return adm1_feed(_ptr(D), _ptr(idx), _ptr(S_in), int(S_in.shape[0]))
+
+
+# ---------------------------------------------------------------------------
+# C-named entry points
+# ---------------------------------------------------------------------------
+def adm1_init(params, opts: adm1_opts, n_max: int) -> int:
+    """Create a context; returns the opaque handle (int)."""
+    if isinstance(params, dict):
+        params = make_params(params)
+    h = ctypes.c_void_p()
+    _check(lib().adm1_init(ctypes.byref(params), ctypes.byref(opts), int(n_max),
+                           ctypes.byref(h)), "adm1_init")
+    return h.value
+
+
+def adm1_set_opts(ctx: int, opts: adm1_opts):
+    _check(lib().adm1_set_opts(ctx, ctypes.byref(opts)), "adm1_set_opts")
+
+
+def adm1_destroy(ctx: int):
+    lib().adm1_destroy(ctx)
+
+
+def adm1_step_particles(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, n, aux=None,
+                        status=None, nsteps=None, stream=None, check=True) -> int:
+    rc = lib().adm1_step_particles(ctx, _ptr(state), int(ld), _ptr(temp_K),
+                                   ctypes.byref(feed), float(dt_days), int(n),
+                                   None if aux is None else ctypes.byref(aux), _ptr(status),
+                                   _ptr(nsteps), _stream(stream))
+    if check:
+        _check(rc, "adm1_step_particles")
+    return rc
+
+
+def adm1_gas_flux(ctx, state, ld, temp_K, V_liq, n, q_gas, q_ch4, totals, stream=None,
+                  check=True) -> int:
+    rc = lib().adm1_gas_flux(ctx, _ptr(state), int(ld), _ptr(temp_K), _ptr(V_liq), int(n),
+                             _ptr(q_gas), _ptr(q_ch4), _ptr(totals), _stream(stream))
+    if check:
+        _check(rc, "adm1_gas_flux")
+    return rc
+
+
+def adm1_rhs(ctx, state, ld, temp_K, feed: adm1_feed, n, dxdt, ld_out, H_out=None,
+             rate_precision=0, status=None, stream=None, check=True) -> int:
+    rc = lib().adm1_rhs(ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed), int(n),
+                        _ptr(dxdt), int(ld_out), _ptr(H_out), int(rate_precision),
+                        _ptr(status), _stream(stream))
+    if check:
+        _check(rc, "adm1_rhs")
+    return rc
+
+
+def adm1_jacobian(ctx, state, ld, temp_K, feed: adm1_feed, n, J, status=None, stream=None,
+                  check=True) -> int:
+    rc = lib().adm1_jacobian(ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed),
+                             int(n), _ptr(J), _ptr(status), _stream(stream))
+    if check:
+        _check(rc, "adm1_jacobian")
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper: a context plus device copies of one workload
+# ---------------------------------------------------------------------------
+class Context:
+    """Owns an adm1 context; methods take torch CUDA tensors."""
+
+    def __init__(self, n_max: int, rtol: float = 1e-8, atol=None, params=None, **opt_kw):
+        self.values = params if isinstance(params, dict) else load_params(params)
+        self.opts = make_opts(rtol=rtol, atol=atol, **opt_kw)
+        self.handle = adm1_init(make_params(self.values), self.opts, n_max)
+        self.n_max = n_max
+
+    def set_opts(self, **kw):
+        cur = dict(rtol=self.opts.rtol, atol=np.array(self.opts.atol),
+                   max_steps=self.opts.max_steps, newton_tol=self.opts.newton_tol,
+                   newton_maxit=self.opts.newton_maxit,
+                   rate_precision=self.opts.rate_precision, variant=self.opts.variant)
+        cur.update(kw)
+        self.opts = make_opts(**cur)
+        adm1_set_opts(self.handle, self.opts)
+
+    def close(self):
+        if self.handle:
+            adm1_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, state, T, D, fidx, S_in, dt, n=None, H=None, hlast=None, status=None,
+             nsteps=None, stream=None):
+        import torch
+        n = state.shape[1] if n is None else n
+        if status is None:
+            status = torch.empty(n, dtype=torch.uint8, device=state.device)
+        feed = feed_struct(D, fidx, S_in)
+        aux = None if H is None and hlast is None else adm1_aux(_ptr(H), _ptr(hlast))
+        adm1_step_particles(self.handle, state, state.shape[1], T, feed, dt, n, aux, status,
+                            nsteps, stream)
+        return status
+
+    def rhs(self, state, T, D, fidx, S_in, n=None, rate_precision=0, stream=None):
+        import torch
+        n = state.shape[1] if n is None else n
+        ld = state.shape[1]
+        dxdt = torch.empty((ND, ld), dtype=torch.float64, device=state.device)
+        H = torch.empty(n, dtype=torch.float64, device=state.device)
+        st = torch.empty(n, dtype=torch.uint8, device=state.device)
+        adm1_rhs(self.handle, state, ld, T, feed_struct(D, fidx, S_in), n, dxdt, ld, H,
+                 rate_precision, st, stream)
+        return dxdt, H, st
+
+    def jacobian(self, state, T, D, fidx, S_in, n=None, stream=None):
+        import torch
+        n = state.shape[1] if n is None else n
+        J = torch.empty((n, ND, ND), dtype=torch.float64, device=state.device)
+        st = torch.empty(n, dtype=torch.uint8, device=state.device)
+        adm1_jacobian(self.handle, state, state.shape[1], T, feed_struct(D, fidx, S_in), n, J,
+                      st, stream)
+        return J, st
+
+    def gas_flux(self, state, T, V_liq=None, n=None, stream=None):
+        import torch
+        n = state.shape[1] if n is None else n
+        q = torch.empty(n, dtype=torch.float64, device=state.device)
+        qc = torch.empty(n, dtype=torch.float64, device=state.device)
+        tot = torch.empty(4, dtype=torch.float64, device=state.device)
+        adm1_gas_flux(self.handle, state, state.shape[1], T, V_liq, n, q, qc, tot, stream)
+        return q, qc, tot

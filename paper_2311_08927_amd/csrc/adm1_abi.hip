@@ -1,0 +1,421 @@
+// C ABI of the ADM1 step (declared in include/adm1.h): argument checking,
+// parameter derivation, context scratch, and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "adm1.h"
+#include "adm1_kernels.h"
+
+using adm1::DevParams;
+
+struct adm1_ctx {
+    DevParams dp;
+    adm1_opts opts;
+    int64_t n_max;
+    int device;
+    int32_t* d_queue;    // work-queue counter
+    double* d_partial;   // gas-flux block partials [kGasBlocks][4]
+    int tuned_variant;   // autotuned step variant (-1: not tuned)
+    int tuned_blocks_per_cu;
+};
+
+namespace {
+
+constexpr int kGasBlocks = 1024;
+
+#define ADM1_PARAM_FIELDS(X)                                                              \
+    X(f_sI_xc) X(f_xI_xc) X(f_ch_xc) X(f_pr_xc) X(f_li_xc) X(N_xc) X(N_I) X(N_aa) X(N_bac) \
+    X(C_xc) X(C_sI) X(C_ch) X(C_pr) X(C_li) X(C_xI) X(C_su) X(C_aa) X(C_fa) X(C_va)      \
+    X(C_bu) X(C_pro) X(C_ac) X(C_bac) X(C_ch4) X(f_fa_li) X(f_h2_su) X(f_bu_su)          \
+    X(f_pro_su) X(f_ac_su) X(f_h2_aa) X(f_va_aa) X(f_bu_aa) X(f_pro_aa) X(f_ac_aa)       \
+    X(f_ac_fa) X(f_h2_fa) X(f_pro_va) X(f_ac_va) X(f_h2_va) X(f_ac_bu) X(f_h2_bu)        \
+    X(f_ac_pro) X(f_h2_pro) X(Y_su) X(Y_aa) X(Y_fa) X(Y_c4) X(Y_pro) X(Y_ac) X(Y_h2)     \
+    X(k_dis) X(k_hyd_ch) X(k_hyd_pr) X(k_hyd_li) X(k_m_su) X(K_S_su) X(k_m_aa)          \
+    X(K_S_aa) X(k_m_fa) X(K_S_fa) X(K_I_h2_fa) X(k_m_c4) X(K_S_c4) X(K_I_h2_c4)          \
+    X(k_m_pro) X(K_S_pro) X(K_I_h2_pro) X(k_m_ac) X(K_S_ac) X(K_I_nh3) X(k_m_h2)        \
+    X(K_S_h2) X(k_dec_su) X(k_dec_aa) X(k_dec_fa) X(k_dec_c4) X(k_dec_pro) X(k_dec_ac)  \
+    X(k_dec_h2) X(K_S_IN) X(pH_UL_aa) X(pH_LL_aa) X(pH_UL_ac) X(pH_LL_ac) X(pH_UL_h2)  \
+    X(pH_LL_h2) X(eps_c4) X(E_a) X(T_ref_kin) X(R) X(T_base) X(K_w_base) X(dH_w)        \
+    X(K_a_va) X(K_a_bu) X(K_a_pro) X(K_a_ac) X(K_a_co2_base) X(dH_a_co2) X(K_a_IN_base) \
+    X(dH_a_IN) X(K_H_h2_base) X(dH_H_h2) X(K_H_ch4_base) X(dH_H_ch4) X(K_H_co2_base)    \
+    X(dH_H_co2) X(p_h2o_base) X(p_h2o_coef) X(k_L_a) X(k_p_per_V_liq) X(V_gas_per_V_liq) \
+    X(P_atm)
+
+const char kParamNames[] =
+#define ADM1_NAME(n) #n ","
+    ADM1_PARAM_FIELDS(ADM1_NAME)
+#undef ADM1_NAME
+    ;
+
+// every field of adm1_params is listed once, in order
+#define ADM1_COUNT(n) +1
+static_assert(sizeof(adm1_params) == sizeof(double) * (0 ADM1_PARAM_FIELDS(ADM1_COUNT)),
+              "adm1_params field list out of sync");
+#undef ADM1_COUNT
+
+enum E {
+    eSsu, eSaa, eSfa, eSva, eSbu, eSpro, eSac, eSh2, eSch4, eSIC, eSIN, eSI, eXxc, eXch,
+    eXpr, eXli, eXsu, eXaa, eXfa, eXc4, eXpro, eXac, eXh2, eXI, eScat, eSan, eNLIQ
+};
+
+// Petersen matrix of eq. 2 (organic entries; the inorganic C and N rows are
+// derived as closures) built from the named parameters.
+void petersen(const adm1_params& p, double nu[eNLIQ][19])
+{
+    std::memset(nu, 0, sizeof(double) * eNLIQ * 19);
+    nu[eXxc][0] = -1; nu[eSI][0] = p.f_sI_xc; nu[eXch][0] = p.f_ch_xc;
+    nu[eXpr][0] = p.f_pr_xc; nu[eXli][0] = p.f_li_xc; nu[eXI][0] = p.f_xI_xc;
+    nu[eXch][1] = -1; nu[eSsu][1] = 1;
+    nu[eXpr][2] = -1; nu[eSaa][2] = 1;
+    nu[eXli][3] = -1; nu[eSsu][3] = 1 - p.f_fa_li; nu[eSfa][3] = p.f_fa_li;
+    nu[eSsu][4] = -1; nu[eSbu][4] = (1 - p.Y_su) * p.f_bu_su;
+    nu[eSpro][4] = (1 - p.Y_su) * p.f_pro_su; nu[eSac][4] = (1 - p.Y_su) * p.f_ac_su;
+    nu[eSh2][4] = (1 - p.Y_su) * p.f_h2_su; nu[eXsu][4] = p.Y_su;
+    nu[eSaa][5] = -1; nu[eSva][5] = (1 - p.Y_aa) * p.f_va_aa;
+    nu[eSbu][5] = (1 - p.Y_aa) * p.f_bu_aa; nu[eSpro][5] = (1 - p.Y_aa) * p.f_pro_aa;
+    nu[eSac][5] = (1 - p.Y_aa) * p.f_ac_aa; nu[eSh2][5] = (1 - p.Y_aa) * p.f_h2_aa;
+    nu[eXaa][5] = p.Y_aa;
+    nu[eSfa][6] = -1; nu[eSac][6] = (1 - p.Y_fa) * p.f_ac_fa;
+    nu[eSh2][6] = (1 - p.Y_fa) * p.f_h2_fa; nu[eXfa][6] = p.Y_fa;
+    nu[eSva][7] = -1; nu[eSpro][7] = (1 - p.Y_c4) * p.f_pro_va;
+    nu[eSac][7] = (1 - p.Y_c4) * p.f_ac_va; nu[eSh2][7] = (1 - p.Y_c4) * p.f_h2_va;
+    nu[eXc4][7] = p.Y_c4;
+    nu[eSbu][8] = -1; nu[eSac][8] = (1 - p.Y_c4) * p.f_ac_bu;
+    nu[eSh2][8] = (1 - p.Y_c4) * p.f_h2_bu; nu[eXc4][8] = p.Y_c4;
+    nu[eSpro][9] = -1; nu[eSac][9] = (1 - p.Y_pro) * p.f_ac_pro;
+    nu[eSh2][9] = (1 - p.Y_pro) * p.f_h2_pro; nu[eXpro][9] = p.Y_pro;
+    nu[eSac][10] = -1; nu[eSch4][10] = 1 - p.Y_ac; nu[eXac][10] = p.Y_ac;
+    nu[eSh2][11] = -1; nu[eSch4][11] = 1 - p.Y_h2; nu[eXh2][11] = p.Y_h2;
+    for (int b = 0; b < 7; ++b) { nu[eXsu + b][12 + b] = -1; nu[eXxc][12 + b] = 1; }
+}
+
+int derive(const adm1_params& p, DevParams& d)
+{
+    std::memset(&d, 0, sizeof(d));
+    // positivity of the constants that divide or set scales
+    const double pos[] = {p.K_S_su, p.K_S_aa, p.K_S_fa, p.K_S_c4, p.K_S_pro, p.K_S_ac,
+                          p.K_S_h2, p.K_I_h2_fa, p.K_I_h2_c4, p.K_I_h2_pro, p.K_I_nh3,
+                          p.K_S_IN, p.eps_c4, p.R, p.T_base, p.T_ref_kin, p.K_w_base,
+                          p.K_a_va, p.K_a_bu, p.K_a_pro, p.K_a_ac, p.K_a_co2_base,
+                          p.K_a_IN_base, p.K_H_h2_base, p.K_H_ch4_base, p.K_H_co2_base,
+                          p.V_gas_per_V_liq, p.P_atm, p.k_L_a};
+    for (double v : pos)
+        if (!(v > 0.0) || !std::isfinite(v)) return ADM1_E_PARAMS;
+    const double nonneg[] = {p.k_dis, p.k_hyd_ch, p.k_hyd_pr, p.k_hyd_li, p.k_m_su, p.k_m_aa,
+                             p.k_m_fa, p.k_m_c4, p.k_m_pro, p.k_m_ac, p.k_m_h2, p.k_dec_su,
+                             p.k_dec_aa, p.k_dec_fa, p.k_dec_c4, p.k_dec_pro, p.k_dec_ac,
+                             p.k_dec_h2, p.k_p_per_V_liq, p.p_h2o_base};
+    for (double v : nonneg)
+        if (!(v >= 0.0) || !std::isfinite(v)) return ADM1_E_PARAMS;
+    const double ll[3] = {p.pH_LL_aa, p.pH_LL_ac, p.pH_LL_h2};
+    const double ul[3] = {p.pH_UL_aa, p.pH_UL_ac, p.pH_UL_h2};
+    for (int k = 0; k < 3; ++k) {
+        if (!(ul[k] > ll[k])) return ADM1_E_PARAMS;
+        d.pH_n[k] = 3.0 / (ul[k] - ll[k]);
+        d.pH_K[k] = std::pow(10.0, -0.5 * (ll[k] + ul[k]));
+        const double r = std::nearbyint(d.pH_n[k]);
+        d.pH_nint[k] = (std::fabs(d.pH_n[k] - r) < 1e-12 && r >= 1 && r <= 4) ? (int)r : 0;
+    }
+
+    double nu[eNLIQ][19];
+    petersen(p, nu);
+    // COD continuity of every process over the COD-bearing entries
+    const int cod[] = {eSsu, eSaa, eSfa, eSva, eSbu, eSpro, eSac, eSh2, eSch4, eSI, eXxc,
+                       eXch, eXpr, eXli, eXsu, eXaa, eXfa, eXc4, eXpro, eXac, eXh2, eXI};
+    for (int j = 0; j < 19; ++j) {
+        double s = 0.0, a = 0.0;
+        for (int i : cod) { s += nu[i][j]; a += std::fabs(nu[i][j]); }
+        if (std::fabs(s) > 1e-12 * (a > 1.0 ? a : 1.0)) return ADM1_E_PARAMS;
+    }
+    // carbon and nitrogen contents; closures
+    double C[eNLIQ] = {0}, N[eNLIQ] = {0};
+    C[eSsu] = p.C_su; C[eSaa] = p.C_aa; C[eSfa] = p.C_fa; C[eSva] = p.C_va; C[eSbu] = p.C_bu;
+    C[eSpro] = p.C_pro; C[eSac] = p.C_ac; C[eSch4] = p.C_ch4; C[eSI] = p.C_sI;
+    C[eXxc] = p.C_xc; C[eXch] = p.C_ch; C[eXpr] = p.C_pr; C[eXli] = p.C_li; C[eXI] = p.C_xI;
+    N[eSaa] = p.N_aa; N[eSI] = p.N_I; N[eXxc] = p.N_xc; N[eXpr] = p.N_aa; N[eXI] = p.N_I;
+    for (int b = eXsu; b <= eXh2; ++b) { C[b] = p.C_bac; N[b] = p.N_bac; }
+    for (int j = 0; j < 19; ++j) {
+        double sc = 0.0, sn = 0.0;
+        for (int i = 0; i < eNLIQ; ++i) { sc += C[i] * nu[i][j]; sn += N[i] * nu[i][j]; }
+        d.nuIC[j] = -sc;
+        d.nuIN[j] = -sn;
+    }
+
+    d.k_dis = p.k_dis; d.k_hyd_ch = p.k_hyd_ch; d.k_hyd_pr = p.k_hyd_pr;
+    d.k_hyd_li = p.k_hyd_li;
+    d.k_m_su = p.k_m_su; d.K_S_su = p.K_S_su; d.k_m_aa = p.k_m_aa; d.K_S_aa = p.K_S_aa;
+    d.k_m_fa = p.k_m_fa; d.K_S_fa = p.K_S_fa; d.K_I_h2_fa = p.K_I_h2_fa;
+    d.k_m_c4 = p.k_m_c4; d.K_S_c4 = p.K_S_c4; d.K_I_h2_c4 = p.K_I_h2_c4;
+    d.k_m_pro = p.k_m_pro; d.K_S_pro = p.K_S_pro; d.K_I_h2_pro = p.K_I_h2_pro;
+    d.k_m_ac = p.k_m_ac; d.K_S_ac = p.K_S_ac; d.K_I_nh3 = p.K_I_nh3;
+    d.k_m_h2 = p.k_m_h2; d.K_S_h2 = p.K_S_h2;
+    d.k_dec[0] = p.k_dec_su; d.k_dec[1] = p.k_dec_aa; d.k_dec[2] = p.k_dec_fa;
+    d.k_dec[3] = p.k_dec_c4; d.k_dec[4] = p.k_dec_pro; d.k_dec[5] = p.k_dec_ac;
+    d.k_dec[6] = p.k_dec_h2;
+    d.K_S_IN = p.K_S_IN; d.eps_c4 = p.eps_c4;
+    const double R100 = 100.0 * p.R;
+    d.Ea_R100 = p.E_a / R100; d.inv_T_ref_kin = 1.0 / p.T_ref_kin;
+    d.inv_T_base = 1.0 / p.T_base; d.R = p.R;
+    d.K_w_base = p.K_w_base; d.dH_w_R100 = p.dH_w / R100;
+    d.K_a_co2_base = p.K_a_co2_base; d.dH_a_co2_R100 = p.dH_a_co2 / R100;
+    d.K_a_IN_base = p.K_a_IN_base; d.dH_a_IN_R100 = p.dH_a_IN / R100;
+    d.K_H_h2_base = p.K_H_h2_base; d.dH_H_h2_R100 = p.dH_H_h2 / R100;
+    d.K_H_ch4_base = p.K_H_ch4_base; d.dH_H_ch4_R100 = p.dH_H_ch4 / R100;
+    d.K_H_co2_base = p.K_H_co2_base; d.dH_H_co2_R100 = p.dH_H_co2 / R100;
+    d.p_h2o_base = p.p_h2o_base; d.p_h2o_coef = p.p_h2o_coef;
+    d.K_a_va = p.K_a_va; d.K_a_bu = p.K_a_bu; d.K_a_pro = p.K_a_pro; d.K_a_ac = p.K_a_ac;
+    d.kLa = p.k_L_a; d.kp = p.k_p_per_V_liq; d.inv_vg = 1.0 / p.V_gas_per_V_liq;
+    d.P_atm = p.P_atm;
+    d.f_sI_xc = p.f_sI_xc; d.f_xI_xc = p.f_xI_xc; d.f_ch_xc = p.f_ch_xc;
+    d.f_pr_xc = p.f_pr_xc; d.f_li_xc = p.f_li_xc; d.f_fa_li = p.f_fa_li;
+    d.nu5_bu = nu[eSbu][4]; d.nu5_pro = nu[eSpro][4]; d.nu5_ac = nu[eSac][4];
+    d.nu5_h2 = nu[eSh2][4]; d.Y_su = p.Y_su;
+    d.nu6_va = nu[eSva][5]; d.nu6_bu = nu[eSbu][5]; d.nu6_pro = nu[eSpro][5];
+    d.nu6_ac = nu[eSac][5]; d.nu6_h2 = nu[eSh2][5]; d.Y_aa = p.Y_aa;
+    d.nu7_ac = nu[eSac][6]; d.nu7_h2 = nu[eSh2][6]; d.Y_fa = p.Y_fa;
+    d.nu8_pro = nu[eSpro][7]; d.nu8_ac = nu[eSac][7]; d.nu8_h2 = nu[eSh2][7];
+    d.Y_c4 = p.Y_c4;
+    d.nu9_ac = nu[eSac][8]; d.nu9_h2 = nu[eSh2][8];
+    d.nu10_ac = nu[eSac][9]; d.nu10_h2 = nu[eSh2][9]; d.Y_pro = p.Y_pro;
+    d.nu11_ch4 = nu[eSch4][10]; d.Y_ac = p.Y_ac;
+    d.nu12_ch4 = nu[eSch4][11]; d.Y_h2 = p.Y_h2;
+    return ADM1_OK;
+}
+
+int apply_opts(const adm1_opts& o, DevParams& d)
+{
+    if (!(o.rtol > 0.0) || !std::isfinite(o.rtol) || o.max_steps <= 0 ||
+        !(o.newton_tol > 0.0) || o.newton_maxit <= 0 ||
+        (o.rate_precision != 0 && o.rate_precision != 1) || o.variant < -1 ||
+        o.variant >= ADM1_VARIANT_COUNT)
+        return ADM1_E_OPTS;
+    for (int k = 0; k < 28; ++k)
+        if (!(o.atol[k] > 0.0) || !std::isfinite(o.atol[k])) return ADM1_E_OPTS;
+    d.rtol = o.rtol;
+    for (int k = 0; k < 28; ++k) d.atol[k] = o.atol[k];
+    d.newton_tol = o.newton_tol;
+    d.max_steps = o.max_steps;
+    d.newton_maxit = o.newton_maxit;
+    return ADM1_OK;
+}
+
+bool is_device(const void* ptr)
+{
+    if (!ptr) return false;
+    hipPointerAttribute_t at;
+    const hipError_t e = hipPointerGetAttributes(&at, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged ||
+           at.type == hipMemoryTypeUnified;
+}
+
+int check_layout(const adm1_ctx* ctx, int64_t ld, int64_t n)
+{
+    if (n < 0 || n > ctx->n_max || ld < n || ld <= 0 || ld % 64 != 0) return ADM1_E_SIZE;
+    return ADM1_OK;
+}
+
+int check_feed(const adm1_feed* feed)
+{
+    if (!feed) return ADM1_E_NULL;
+    if (!feed->D || !feed->idx || !feed->S_in) return ADM1_E_NULL;
+    if (feed->n_feed < 1) return ADM1_E_FEED;
+    if (!is_device(feed->D) || !is_device(feed->idx) || !is_device(feed->S_in))
+        return ADM1_E_NOT_DEVICE;
+    return ADM1_OK;
+}
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? ADM1_OK : (int)e; }
+
+}  // namespace
+
+extern "C" {
+
+const char* adm1_param_names(void) { return kParamNames; }
+
+const char* adm1_strerror(int code)
+{
+    switch (code) {
+    case ADM1_OK: return "ok";
+    case ADM1_E_NULL: return "a required pointer is NULL";
+    case ADM1_E_SIZE: return "bad size: need 0 <= n <= n_max, ld >= n, ld % 64 == 0";
+    case ADM1_E_NOT_DEVICE: return "pointer is not device memory";
+    case ADM1_E_PARAMS: return "parameter set fails COD continuity or a range check";
+    case ADM1_E_OPTS: return "invalid integration options";
+    case ADM1_E_FEED: return "invalid feed table";
+    case ADM1_E_NOMEM: return "context scratch allocation failed";
+    case ADM1_E_VARIANT: return "unknown step-kernel variant";
+    case ADM1_E_DT: return "dt must be positive and finite";
+    default: break;
+    }
+    if (code > 0) return hipGetErrorString((hipError_t)code);
+    return "unknown error";
+}
+
+int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx** out)
+{
+    if (!p || !o || !out) return ADM1_E_NULL;
+    if (n_max < 0) return ADM1_E_SIZE;
+    adm1_ctx* c = new (std::nothrow) adm1_ctx;
+    if (!c) return ADM1_E_NOMEM;
+    std::memset(c, 0, sizeof(*c));
+    int rc = derive(*p, c->dp);
+    if (rc == ADM1_OK) rc = apply_opts(*o, c->dp);
+    if (rc != ADM1_OK) { delete c; return rc; }
+    c->opts = *o;
+    c->n_max = n_max;
+    c->tuned_variant = -1;
+    c->tuned_blocks_per_cu = 0;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return ADM1_E_NOMEM; }
+    if (hipMalloc(&c->d_queue, 64 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->d_partial, kGasBlocks * 4 * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->d_queue) (void)hipFree(c->d_queue);
+        if (c->d_partial) (void)hipFree(c->d_partial);
+        delete c;
+        return ADM1_E_NOMEM;
+    }
+    if (hipMemset(c->d_queue, 0, 64 * sizeof(int32_t)) != hipSuccess) {
+        (void)hipFree(c->d_queue);
+        (void)hipFree(c->d_partial);
+        delete c;
+        return ADM1_E_NOMEM;
+    }
+    *out = c;
+    return ADM1_OK;
+}
+
+int adm1_set_opts(adm1_ctx* ctx, const adm1_opts* o)
+{
+    if (!ctx || !o) return ADM1_E_NULL;
+    DevParams d = ctx->dp;
+    const int rc = apply_opts(*o, d);
+    if (rc != ADM1_OK) return rc;
+    ctx->dp = d;
+    ctx->opts = *o;
+    return ADM1_OK;
+}
+
+void adm1_destroy(adm1_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipFree(ctx->d_queue);
+    (void)hipFree(ctx->d_partial);
+    delete ctx;
+}
+
+int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,
+                        const adm1_feed* feed, double dt_days, int64_t n, adm1_aux* aux,
+                        uint8_t* status, int32_t* nsteps, void* stream)
+{
+    if (!ctx || !state || !temp_K || !status) return ADM1_E_NULL;
+    int rc = check_layout(ctx, ld, n);
+    if (rc) return rc;
+    if (!(dt_days > 0.0) || !std::isfinite(dt_days)) return ADM1_E_DT;
+    rc = check_feed(feed);
+    if (rc) return rc;
+    if (!is_device(state) || !is_device(temp_K) || !is_device(status)) return ADM1_E_NOT_DEVICE;
+    if (nsteps && !is_device(nsteps)) return ADM1_E_NOT_DEVICE;
+    if (aux) {
+        if ((aux->H && !is_device(aux->H)) || (aux->h_last && !is_device(aux->h_last)))
+            return ADM1_E_NOT_DEVICE;
+    }
+    if (n == 0) return ADM1_OK;
+    adm1::StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.p = ctx->dp;
+    a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.D = feed->D; a.fidx = feed->idx;
+    a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.dt = dt_days;
+    a.H = aux ? aux->H : nullptr;
+    a.hlast = aux ? aux->h_last : nullptr;
+    a.status = status; a.nsteps = nsteps; a.queue = ctx->d_queue;
+    int variant = ctx->opts.variant;
+    if (variant < 0) variant = ctx->tuned_variant >= 0 ? ctx->tuned_variant : ADM1_VARIANT_SPARSE1;
+    hipStream_t s = (hipStream_t)stream;
+    switch (variant) {
+    case ADM1_VARIANT_DENSE1:
+        return hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, false, s));
+    case ADM1_VARIANT_SPARSE1:
+        return hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, true, s));
+    case ADM1_VARIANT_SPARSE2:
+        return hip_rc(adm1::launch_step_sparse2(a, ctx->opts.rate_precision,
+                                                ctx->tuned_blocks_per_cu, s));
+    default:
+        return ADM1_E_VARIANT;
+    }
+}
+
+int adm1_gas_flux(adm1_ctx* ctx, const double* state, int64_t ld, const double* temp_K,
+                  const double* V_liq, int64_t n, double* q_gas, double* q_ch4,
+                  double* totals, void* stream)
+{
+    if (!ctx || !state || !temp_K || !totals) return ADM1_E_NULL;
+    const int rc = check_layout(ctx, ld, n);
+    if (rc) return rc;
+    if (!is_device(state) || !is_device(temp_K) || !is_device(totals))
+        return ADM1_E_NOT_DEVICE;
+    if ((V_liq && !is_device(V_liq)) || (q_gas && !is_device(q_gas)) ||
+        (q_ch4 && !is_device(q_ch4)))
+        return ADM1_E_NOT_DEVICE;
+    adm1::GasArgs a;
+    a.p = ctx->dp;
+    a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.V_liq = V_liq;
+    a.q_gas = q_gas; a.q_ch4 = q_ch4; a.partial = ctx->d_partial;
+    // fixed partition of the particles over the blocks: depends on n only
+    int64_t chunk = (n + kGasBlocks - 1) / kGasBlocks;
+    chunk = (chunk + 255) / 256 * 256;
+    if (chunk < 256) chunk = 256;
+    a.chunk = chunk;
+    int nblocks = (int)((n + chunk - 1) / chunk);
+    if (nblocks < 1) nblocks = 1;
+    return hip_rc(adm1::launch_gasflux(a, nblocks, totals, (hipStream_t)stream));
+}
+
+int adm1_rhs(adm1_ctx* ctx, const double* state, int64_t ld, const double* temp_K,
+             const adm1_feed* feed, int64_t n, double* dxdt, int64_t ld_out, double* H_out,
+             int32_t rate_precision, uint8_t* status, void* stream)
+{
+    if (!ctx || !state || !temp_K || !dxdt) return ADM1_E_NULL;
+    int rc = check_layout(ctx, ld, n);
+    if (rc) return rc;
+    if (ld_out < n) return ADM1_E_SIZE;
+    if (rate_precision != 0 && rate_precision != 1) return ADM1_E_OPTS;
+    rc = check_feed(feed);
+    if (rc) return rc;
+    if (!is_device(state) || !is_device(temp_K) || !is_device(dxdt)) return ADM1_E_NOT_DEVICE;
+    if ((H_out && !is_device(H_out)) || (status && !is_device(status)))
+        return ADM1_E_NOT_DEVICE;
+    adm1::RhsArgs a;
+    a.p = ctx->dp;
+    a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.D = feed->D; a.fidx = feed->idx;
+    a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.dxdt = dxdt; a.ld_out = ld_out; a.H_out = H_out;
+    a.status = status;
+    return hip_rc(adm1::launch_rhs(a, rate_precision, (hipStream_t)stream));
+}
+
+int adm1_jacobian(adm1_ctx* ctx, const double* state, int64_t ld, const double* temp_K,
+                  const adm1_feed* feed, int64_t n, double* J, uint8_t* status, void* stream)
+{
+    if (!ctx || !state || !temp_K || !J) return ADM1_E_NULL;
+    int rc = check_layout(ctx, ld, n);
+    if (rc) return rc;
+    rc = check_feed(feed);
+    if (rc) return rc;
+    if (!is_device(state) || !is_device(temp_K) || !is_device(J)) return ADM1_E_NOT_DEVICE;
+    if (status && !is_device(status)) return ADM1_E_NOT_DEVICE;
+    adm1::RhsArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.p = ctx->dp;
+    a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.D = feed->D; a.fidx = feed->idx;
+    a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.status = status;
+    return hip_rc(adm1::launch_jacobian(a, J, (hipStream_t)stream));
+}
+
+}  // extern "C"

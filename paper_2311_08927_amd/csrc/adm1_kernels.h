@@ -1,0 +1,62 @@
+// Kernel argument blocks and launchers of the ADM1 step (internal header).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adm1_devparams.h"
+
+namespace adm1 {
+
+struct StepArgs {
+    DevParams p;
+    double* state;          // [35][ld]
+    int64_t ld, n;
+    const double* T;        // [n]
+    const double* D;        // [n]
+    const int32_t* fidx;    // [n]
+    const double* S_in;     // [n_feed][26]
+    int64_t n_feed;
+    double dt;
+    double* H;              // [n] nullable
+    double* hlast;          // [n] nullable
+    uint8_t* status;        // [n]
+    int32_t* nsteps;        // [3][ld] nullable
+    int32_t* queue;         // work-queue counter (persistent kernels)
+    const int32_t* index;   // optional particle index list (nullable: identity)
+    const int32_t* index_count;  // device count of the index list (with index)
+};
+
+struct RhsArgs {
+    DevParams p;
+    const double* state;
+    int64_t ld, n;
+    const double* T;
+    const double* D;
+    const int32_t* fidx;
+    const double* S_in;
+    int64_t n_feed;
+    double* dxdt;
+    int64_t ld_out;
+    double* H_out;
+    uint8_t* status;
+};
+
+struct GasArgs {
+    DevParams p;
+    const double* state;
+    int64_t ld, n, chunk;
+    const double* T;
+    const double* V_liq;
+    double* q_gas;
+    double* q_ch4;
+    double* partial;  // [nblocks][4]
+};
+
+hipError_t launch_step1(const StepArgs& a, int rate_precision, bool sparse, hipStream_t s);
+hipError_t launch_step_sparse2(const StepArgs& a, int rate_precision, int blocks_per_cu,
+                               hipStream_t s);
+hipError_t launch_rhs(const RhsArgs& a, int rate_precision, hipStream_t s);
+hipError_t launch_jacobian(const RhsArgs& a, double* J, hipStream_t s);
+hipError_t launch_gasflux(const GasArgs& a, int nblocks, double* totals, hipStream_t s);
+
+}  // namespace adm1

@@ -1,0 +1,295 @@
+"""Generate the Newton-matrix code of the ADM1 Rosenbrock step.
+
+The Rosenbrock stage equations need (alpha I - J) u = r with J the total
+derivative of the 28 differential right-hand sides, the algebraic unknowns
+z = (S_H+, S_h2) being eliminated through eq. 7 and eq. 8.  Instead of the
+dense reduced J, the kernels solve the equivalent sparse bordered system
+
+    [ alpha I - f_y   -f_z ] [u]   [r]
+    [   g_y            g_z ] [w] = [0]
+
+(f_y, f_z partial derivatives at fixed z; g the eq. 7 and eq. 8 residuals),
+whose 30x30 pattern is fixed by the model structure.  This script holds that
+structure and emits:
+
+  adm1_jac_dense.inc  -- fills a dense row-major M[30*30] (one lane per
+                         particle, partial pivoting);
+  adm1_jac_sparse.inc -- the two-lanes-per-particle kernel body pieces: the
+                         static-order sparse LU, with rows split over a lane
+                         pair (see emit_sparse).
+
+Run: python gen_jac.py   (writes the .inc files next to this script)
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+Y = ["Ssu", "Saa", "Sfa", "Sva", "Sbu", "Spro", "Sac", "Sch4", "SIC", "SIN", "SI", "Xxc",
+     "Xch", "Xpr", "Xli", "Xsu", "Xaa", "Xfa", "Xc4", "Xpro", "Xac", "Xh2", "XI", "Scat",
+     "San", "Gh2", "Gch4", "Gco2"]
+Z = ["H", "Sh2"]
+VARS = Y + Z
+NV = len(VARS)  # 30
+LIQ = Y[:25]
+GAS = Y[25:]
+
+# rate -> variables it depends on (partials named J_<rate>_<var> in struct Partials)
+RATES = {
+    "dis": ["Xxc"], "hch": ["Xch"], "hpr": ["Xpr"], "hli": ["Xli"],
+    "su": ["Ssu", "Xsu", "SIN", "H"],
+    "aa": ["Saa", "Xaa", "SIN", "H"],
+    "fa": ["Sfa", "Xfa", "SIN", "H", "Sh2"],
+    "va": ["Sva", "Sbu", "Xc4", "SIN", "H", "Sh2"],
+    "bu": ["Sva", "Sbu", "Xc4", "SIN", "H", "Sh2"],
+    "pro": ["Spro", "Xpro", "SIN", "H", "Sh2"],
+    "ac": ["Sac", "Xac", "SIN", "H"],
+    "h2": ["Sh2", "Xh2", "SIN", "H"],
+    "dsu": ["Xsu"], "daa": ["Xaa"], "dfa": ["Xfa"], "dc4": ["Xc4"], "dpro": ["Xpro"],
+    "dac": ["Xac"], "dh2": ["Xh2"],
+    "T8": ["Sh2", "Gh2"], "T9": ["Sch4", "Gch4"], "T10": ["SIC", "H", "Gco2"],
+    "QGh2": ["Gh2", "Gch4", "Gco2"], "QGch4": ["Gh2", "Gch4", "Gco2"],
+    "QGco2": ["Gh2", "Gch4", "Gco2"],
+    "E7": ["Scat", "San", "SIN", "SIC", "Sac", "Spro", "Sbu", "Sva", "H"],
+}
+PROCS = ["dis", "hch", "hpr", "hli", "su", "aa", "fa", "va", "bu", "pro", "ac", "h2", "dsu",
+         "daa", "dfa", "dc4", "dpro", "dac", "dh2"]
+
+# Petersen matrix: liquid row -> [(coefficient C expression, rate)]
+NU = {
+    "Ssu": [("1.0", "hch"), ("(1.0 - p.f_fa_li)", "hli"), ("-1.0", "su")],
+    "Saa": [("1.0", "hpr"), ("-1.0", "aa")],
+    "Sfa": [("p.f_fa_li", "hli"), ("-1.0", "fa")],
+    "Sva": [("p.nu6_va", "aa"), ("-1.0", "va")],
+    "Sbu": [("p.nu5_bu", "su"), ("p.nu6_bu", "aa"), ("-1.0", "bu")],
+    "Spro": [("p.nu5_pro", "su"), ("p.nu6_pro", "aa"), ("p.nu8_pro", "va"), ("-1.0", "pro")],
+    "Sac": [("p.nu5_ac", "su"), ("p.nu6_ac", "aa"), ("p.nu7_ac", "fa"), ("p.nu8_ac", "va"),
+            ("p.nu9_ac", "bu"), ("p.nu10_ac", "pro"), ("-1.0", "ac")],
+    "Sch4": [("p.nu11_ch4", "ac"), ("p.nu12_ch4", "h2"), ("-1.0", "T9")],
+    "SIC": [(f"p.nuIC[{j}]", r) for j, r in enumerate(PROCS)] + [("-1.0", "T10")],
+    "SIN": [(f"p.nuIN[{j}]", r) for j, r in enumerate(PROCS)],
+    "SI": [("p.f_sI_xc", "dis")],
+    "Xxc": [("-1.0", "dis")] + [("1.0", r) for r in PROCS[12:]],
+    "Xch": [("p.f_ch_xc", "dis"), ("-1.0", "hch")],
+    "Xpr": [("p.f_pr_xc", "dis"), ("-1.0", "hpr")],
+    "Xli": [("p.f_li_xc", "dis"), ("-1.0", "hli")],
+    "Xsu": [("p.Y_su", "su"), ("-1.0", "dsu")],
+    "Xaa": [("p.Y_aa", "aa"), ("-1.0", "daa")],
+    "Xfa": [("p.Y_fa", "fa"), ("-1.0", "dfa")],
+    "Xc4": [("p.Y_c4", "va"), ("p.Y_c4", "bu"), ("-1.0", "dc4")],
+    "Xpro": [("p.Y_pro", "pro"), ("-1.0", "dpro")],
+    "Xac": [("p.Y_ac", "ac"), ("-1.0", "dac")],
+    "Xh2": [("p.Y_h2", "h2"), ("-1.0", "dh2")],
+    "XI": [("p.f_xI_xc", "dis")],
+    "Scat": [], "San": [],
+    # gas rows: f_G = inv_vg (-q G + T)
+    "Gh2": [("-p.inv_vg", "QGh2"), ("p.inv_vg", "T8")],
+    "Gch4": [("-p.inv_vg", "QGch4"), ("p.inv_vg", "T9")],
+    "Gco2": [("-p.inv_vg", "QGco2"), ("p.inv_vg", "T10")],
+}
+# eq. 8 residual E8 = D (S_h2,in - S_h2) + sum_j nu_h2,j rho_j - T8
+NU_H2 = [("p.nu5_h2", "su"), ("p.nu6_h2", "aa"), ("p.nu7_h2", "fa"), ("p.nu8_h2", "va"),
+         ("p.nu9_h2", "bu"), ("p.nu10_h2", "pro"), ("-1.0", "h2"), ("-1.0", "T8")]
+
+
+def partial_names():
+    return [f"J_{r}_{v}" for r, vs in RATES.items() for v in vs]
+
+
+def entries():
+    """Structural entries of the bordered matrix M as
+    {(row, col): [terms]} with terms (sign, coef, rate) meaning
+    sign * coef * J_rate_col, plus the diagonal constants."""
+    M = {}
+
+    def add(r, c, term):
+        M.setdefault((r, c), []).append(term)
+
+    for i, yname in enumerate(Y):
+        # alpha I (and + D for the liquid dilution term)
+        add(i, i, ("diag_liq" if yname in LIQ else "diag_gas",))
+        for coef, rate in NU[yname]:
+            for v in RATES[rate]:
+                add(i, VARS.index(v), ("-", coef, rate))
+    r7 = NV - 2
+    for v in RATES["E7"]:
+        add(r7, VARS.index(v), ("+", "1.0", "E7"))
+    r8 = NV - 1
+    # M row = -dE8/dv (+ D on the S_h2 column)
+    add(r8, VARS.index("Sh2"), ("D",))
+    for coef, rate in NU_H2:
+        for v in RATES[rate]:
+            add(r8, VARS.index(v), ("-", coef, rate))
+    return M
+
+
+def expr(terms, col):
+    parts = []
+    for t in terms:
+        if t[0] == "diag_liq":
+            parts.append("(alpha + D)")
+        elif t[0] == "diag_gas":
+            parts.append("alpha")
+        elif t[0] == "D":
+            parts.append("D")
+        else:
+            sign, coef, rate = t
+            name = f"d.J_{rate}_{VARS[col]}"
+            if coef == "1.0":
+                parts.append(("-" if sign == "-" else "+") + name)
+            elif coef == "-1.0":
+                parts.append(("+" if sign == "-" else "-") + name)
+            else:
+                parts.append(f"{'-' if sign == '-' else '+'}({coef}) * {name}")
+    s = " ".join(parts)
+    return s[1:] if s.startswith("+") else s
+
+
+def emit_partials_struct():
+    lines = ["// partial derivatives of every rate in its inputs (generated list)",
+             "struct Partials {"]
+    names = partial_names()
+    for k in range(0, len(names), 6):
+        lines.append("    double " + ", ".join(names[k:k + 6]) + ";")
+    lines.append("};")
+    return "\n".join(lines)
+
+
+def emit_dense():
+    M = entries()
+    out = ["// Generated by gen_jac.py: dense bordered Newton matrix, row-major 30x30.",
+           "// Expects: Partials d, DevParams p, double alpha, double D, double* M",
+           "// (zeroed by the caller).", f"// structural nonzeros: {len(M)}"]
+    for (r, c) in sorted(M):
+        out.append(f"M[{r * NV + c}] = {expr(M[(r, c)], c)};")
+    return "\n".join(out) + "\n"
+
+
+def analyze():
+    """Static elimination order (greedy Markowitz on the pattern, the two
+    constraint rows/columns last) and the resulting LU pattern with fill.
+    Pivots stay on the diagonal of the bordered system (row E7 with column
+    S_H+, row E8 with column S_h2)."""
+    M = entries()
+    pat = {(r, c) for (r, c) in M}
+    remaining = list(range(NV - 2))
+    order = []
+    cur = set(pat)
+    while remaining:
+        best = None
+        for k in remaining:
+            rows = [i for i in remaining + [NV - 2, NV - 1] if i != k and (i, k) in cur]
+            cols = [j for j in remaining + [NV - 2, NV - 1] if j != k and (k, j) in cur]
+            score = (len(rows) * len(cols), len(rows) + len(cols), k)
+            if best is None or score < best[0]:
+                best = (score, k, rows, cols)
+        _, k, rows, cols = best
+        for i in rows:
+            for j in cols:
+                cur.add((i, j))
+        order.append(k)
+        remaining.remove(k)
+    for k in (NV - 2, NV - 1):
+        if k == NV - 2:
+            rows = [NV - 1] if (NV - 1, k) in cur else []
+            cols = [NV - 1] if (k, NV - 1) in cur else []
+            for i in rows:
+                for j in cols:
+                    cur.add((i, j))
+        order.append(k)
+    pos = {v: p for p, v in enumerate(order)}
+    L = {k: [i for i in order if pos[i] > pos[k] and (i, k) in cur] for k in order}
+    U = {k: [j for j in order if pos[j] > pos[k] and (k, j) in cur] for k in order}
+    return order, cur, L, U
+
+
+def lu_counts():
+    order, cur, L, U = analyze()
+    nnzL = sum(len(v) for v in L.values())
+    nnzU = sum(len(v) for v in U.values())
+    factor = sum(1 + len(L[k]) + 2 * len(L[k]) * len(U[k]) for k in order)
+    solve = 2 * nnzL + 2 * nnzU + NV
+    return dict(nnz_struct=len(entries()), nnz_lu=len(cur), nnz_L=nnzL, nnz_U=nnzU,
+                factor_flops=factor, solve_flops=solve, order=[VARIABLES_NAME(v) for v in order])
+
+
+def VARIABLES_NAME(v):
+    return VARS[v] if v < NY_ else ("E7/H" if v == NV - 2 else "E8/Sh2")
+
+
+NY_ = 28
+
+
+def assembly_flops():
+    """Flops of the generated assembly expressions (unit coefficients: 1 add;
+    others: 1 mul + 1 add)."""
+    M = entries()
+    n = 0
+    for terms in M.values():
+        for t in terms:
+            if t[0] in ("diag_liq",):
+                n += 1
+            elif len(t) == 3:
+                n += 1 if t[1] in ("1.0", "-1.0") else 2
+    return n
+
+
+def emit_sparse1():
+    """One lane per particle: the bordered matrix as named scalars m_r_c, the
+    static-order LU, and a solve on b[30] (original variable order)."""
+    order, cur, L, U = analyze()
+    M = entries()
+    out = ["// Generated by gen_jac.py: sparse bordered Newton matrix, static-order LU.",
+           f"// structural nonzeros {len(M)}, with fill {len(cur)}",
+           "#define ADM1_SP_DECL \\"]
+    names = sorted(cur)
+    for k in range(0, len(names), 8):
+        out.append("    double " + ", ".join(f"m_{r}_{c}" for r, c in names[k:k + 8]) + "; \\")
+    out.append("    double " + ", ".join(f"iv_{k}" for k in range(NV)) + ";")
+    out.append("#define ADM1_SP_BUILD(alpha, D) \\")
+    for (r, c) in names:
+        e = expr(M[(r, c)], c) if (r, c) in M else "0.0"
+        e = e.replace("alpha", "(alpha)").replace("(alpha + D)", "((alpha) + (D))")
+        out.append(f"    m_{r}_{c} = {e}; \\")
+    out.append("    (void)0")
+    out.append("#define ADM1_SP_FACTOR(ok) \\")
+    for k in order:
+        out.append(f"    iv_{k} = 1.0 / m_{k}_{k}; ok = ok && isfinite(iv_{k}); \\")
+        for i in L[k]:
+            out.append(f"    m_{i}_{k} *= iv_{k}; \\")
+        for i in L[k]:
+            for j in U[k]:
+                out.append(f"    m_{i}_{j} -= m_{i}_{k} * m_{k}_{j}; \\")
+    out.append("    (void)0")
+    out.append("#define ADM1_SP_SOLVE(b) \\")
+    for k in order:
+        for i in L[k]:
+            out.append(f"    b[{i}] -= m_{i}_{k} * b[{k}]; \\")
+    for k in reversed(order):
+        terms = "".join(f" - m_{k}_{j} * b[{j}]" for j in U[k])
+        out.append(f"    b[{k}] = (b[{k}]{terms}) * iv_{k}; \\")
+    out.append("    (void)0")
+    return "\n".join(out) + "\n"
+
+
+def main():
+    with open(os.path.join(HERE, "adm1_partials.inc"), "w") as fh:
+        fh.write("// Generated by gen_jac.py -- do not edit.\n" + emit_partials_struct() + "\n")
+    with open(os.path.join(HERE, "adm1_jac_dense.inc"), "w") as fh:
+        fh.write(emit_dense())
+    with open(os.path.join(HERE, "adm1_jac_sparse1.inc"), "w") as fh:
+        fh.write(emit_sparse1())
+    stats = lu_counts()
+    stats["assembly_flops"] = assembly_flops()
+    import json
+    with open(os.path.join(HERE, "adm1_lu_stats.json"), "w") as fh:
+        json.dump(stats, fh, indent=1)
+    if "--stats" in sys.argv:
+        print(json.dumps({k: v for k, v in stats.items() if k != "order"}))
+        print("order:", " ".join(stats["order"]))
+
+
+if __name__ == "__main__":
+    main()
