@@ -19,6 +19,9 @@ struct adm1_ctx {
     int device;
     int32_t* d_queue;    // work-queue counter
     double* d_partial;   // gas-flux block partials [kGasBlocks][4]
+    double* d_work;      // stage vectors of the two-lane step kernel
+    DevParams* d_params; // device copy of dp
+    int64_t work_blocks;
     int tuned_variant;   // autotuned step variant (-1: not tuned)
     int tuned_blocks_per_cu;
 };
@@ -198,6 +201,7 @@ int apply_opts(const adm1_opts& o, DevParams& d)
     d.rtol = o.rtol;
     for (int k = 0; k < 28; ++k) d.atol[k] = o.atol[k];
     d.newton_tol = o.newton_tol;
+    d.newton_qtol = 0.1 * std::sqrt(o.newton_tol);
     d.max_steps = o.max_steps;
     d.newton_maxit = o.newton_maxit;
     return ADM1_OK;
@@ -273,18 +277,28 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
     c->n_max = n_max;
     c->tuned_variant = -1;
     c->tuned_blocks_per_cu = 0;
-    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return ADM1_E_NOMEM; }
-    if (hipMalloc(&c->d_queue, 64 * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&c->d_partial, kGasBlocks * 4 * sizeof(double)) != hipSuccess) {
+    int ncu = 0;
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess) {
         (void)hipGetLastError();
-        if (c->d_queue) (void)hipFree(c->d_queue);
-        if (c->d_partial) (void)hipFree(c->d_partial);
         delete c;
         return ADM1_E_NOMEM;
     }
-    if (hipMemset(c->d_queue, 0, 64 * sizeof(int32_t)) != hipSuccess) {
-        (void)hipFree(c->d_queue);
-        (void)hipFree(c->d_partial);
+    c->work_blocks = adm1::sparse2_max_blocks(ncu);
+    const size_t work_bytes = (size_t)adm1::sparse2_work_doubles(c->work_blocks) * sizeof(double);
+    if (hipMalloc(&c->d_queue, 64 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->d_partial, kGasBlocks * 4 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_work, work_bytes) != hipSuccess ||
+        hipMalloc(&c->d_params, sizeof(DevParams)) != hipSuccess ||
+        hipMemcpy(c->d_params, &c->dp, sizeof(DevParams), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemset(c->d_queue, 0, 64 * sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->d_queue) (void)hipFree(c->d_queue);
+        if (c->d_partial) (void)hipFree(c->d_partial);
+        if (c->d_work) (void)hipFree(c->d_work);
+        if (c->d_params) (void)hipFree(c->d_params);
         delete c;
         return ADM1_E_NOMEM;
     }
@@ -298,6 +312,8 @@ int adm1_set_opts(adm1_ctx* ctx, const adm1_opts* o)
     DevParams d = ctx->dp;
     const int rc = apply_opts(*o, d);
     if (rc != ADM1_OK) return rc;
+    if (hipMemcpy(ctx->d_params, &d, sizeof(DevParams), hipMemcpyHostToDevice) != hipSuccess)
+        return (int)hipGetLastError();
     ctx->dp = d;
     ctx->opts = *o;
     return ADM1_OK;
@@ -308,6 +324,8 @@ void adm1_destroy(adm1_ctx* ctx)
     if (!ctx) return;
     (void)hipFree(ctx->d_queue);
     (void)hipFree(ctx->d_partial);
+    (void)hipFree(ctx->d_work);
+    (void)hipFree(ctx->d_params);
     delete ctx;
 }
 
@@ -336,6 +354,7 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
     a.H = aux ? aux->H : nullptr;
     a.hlast = aux ? aux->h_last : nullptr;
     a.status = status; a.nsteps = nsteps; a.queue = ctx->d_queue;
+    a.work = ctx->d_work; a.work_blocks = ctx->work_blocks; a.pdev = ctx->d_params;
     int variant = ctx->opts.variant;
     if (variant < 0) variant = ctx->tuned_variant >= 0 ? ctx->tuned_variant : ADM1_VARIANT_SPARSE1;
     hipStream_t s = (hipStream_t)stream;

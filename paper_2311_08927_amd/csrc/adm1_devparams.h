@@ -48,6 +48,7 @@ typedef struct DevParams {
     double rtol;
     double atol[28];
     double newton_tol;
+    double newton_qtol;  // 0.1 sqrt(newton_tol): stop once a Newton correction is below it
     int max_steps, newton_maxit;
 } DevParams;
 

@@ -98,7 +98,7 @@ __device__ static double initial_step(const DevParams& p, const TConst& c, const
     for (int i = 0; i < NY; ++i) f1[i] -= f0[i];
     const double d2 = rms_scaled(p, f1, y0) / h0;
     const double dm = fmax(d1, d2);
-    const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 0.2);
+    const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : exp(0.2 * log(0.01 / dm));
     return fmin(fmin(100.0 * h0, h1), dt);
 }
 

@@ -61,8 +61,9 @@ __device__ __forceinline__ TConst tconst(const DevParams& p, double T)
 // Eq. 7: charge balance E(S_H+) and dE/dS_H+.  The ions are the equilibrium
 // fractions K/(K + S_H+) of their totals.
 // ---------------------------------------------------------------------------
+template <typename Y>
 __device__ __forceinline__ double charge_balance(const DevParams& p, const TConst& c,
-                                                 const double* y, double H, double& dE)
+                                                 const Y& y, double H, double& dE)
 {
     const double iIN = 1.0 / (c.K_a_IN + H), iCO2 = 1.0 / (c.K_a_co2 + H);
     const double iac = 1.0 / (p.K_a_ac + H), ipro = 1.0 / (p.K_a_pro + H);
@@ -84,7 +85,8 @@ __device__ __forceinline__ double charge_balance(const DevParams& p, const TCons
 // for non-negative totals, so iterates left of the root climb monotonically
 // onto it; a step from the right may overshoot left, and steps are clamped
 // to a factor 10 either way to stay positive.  Returns 0 on convergence.
-__device__ __forceinline__ int solve_H(const DevParams& p, const TConst& c, const double* y,
+template <typename Y>
+__device__ __forceinline__ int solve_H(const DevParams& p, const TConst& c, const Y& y,
                                        double& H, int& iters)
 {
     double h = (H > 0.0 && H < 1e3) ? H : 1e-7;
@@ -96,7 +98,7 @@ __device__ __forceinline__ int solve_H(const DevParams& p, const TConst& c, cons
         if (!(hn >= 0.1 * h)) hn = 0.1 * h;
         else if (hn > 10.0 * h) hn = 10.0 * h;
         ++iters;
-        const bool done = fabs(hn - h) <= p.newton_tol * hn;
+        const bool done = fabs(hn - h) <= p.newton_qtol * hn;
         h = hn;
         if (done) {
             H = h;
@@ -142,7 +144,7 @@ __device__ __forceinline__ int solve_Sh2(const DevParams& p, const H2Terms& t, d
         double sn = s - E / dE;
         if (!(sn > lo)) sn = 0.5 * (s + lo);
         ++iters;
-        const bool done = fabs(sn - s) <= p.newton_tol * fabs(sn) + 1e-30;
+        const bool done = fabs(sn - s) <= p.newton_qtol * fabs(sn) + 1e-30;
         s = sn;
         if (done) {
             S = s;
@@ -162,7 +164,7 @@ __device__ __forceinline__ R inhib_pH(R H, double K, double n, int nint)
     else if (nint == 2) rn = r * r;
     else if (nint == 3) rn = r * r * r;
     else if (nint == 4) { const R r2 = r * r; rn = r2 * r2; }
-    else rn = pow(r, (R)n);
+    else rn = exp2((R)n * log2(r));
     return (R)1 / ((R)1 + rn);
 }
 
@@ -173,10 +175,24 @@ __device__ __forceinline__ R inhib_pH(R H, double K, double n, int nint)
 // H and Sh2 carry the warm starts in and the roots out.  Returns 0, or 1
 // when an algebraic solve fails.
 // ---------------------------------------------------------------------------
+// Inflow term D S_in of state row k, read from the feed table.
+struct FeedInflow {
+    double D;
+    const double* sin;
+    __device__ __forceinline__ double operator()(int k) const { return D * sin[k]; }
+};
+
 template <typename R>
 __device__ __forceinline__ int rhs(const DevParams& p, const TConst& c, const double* y,
                                    double D, const double* sin, double& H, double& Sh2,
-                                   double* f, int& iters)
+                                   double* f, int& iters);
+
+// Right-hand side with the inflow terms D S_in supplied by `inflow` (one
+// accessor per storage layout of the feed).
+template <typename R, typename Y, typename Inflow, typename Out>
+__device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const Y& y,
+                                      double D, const Inflow& inflow, double& H, double& Sh2,
+                                      const Out& out, int& iters)
 {
     if (solve_H(p, c, y, H, iters)) return 1;
     const R a = (R)c.arr;
@@ -221,7 +237,7 @@ __device__ __forceinline__ int rhs(const DevParams& p, const TConst& c, const do
 
     // eq. 8 (FP64) with the rate factors above
     H2Terms t;
-    t.base = D * sin[ROW_SH2] + p.nu5_h2 * (double)rho[4] + p.nu6_h2 * (double)rho[5];
+    t.base = inflow(ROW_SH2) + p.nu5_h2 * (double)rho[4] + p.nu6_h2 * (double)rho[5];
     t.c7 = p.nu7_h2 * (double)b7;
     t.c8 = p.nu8_h2 * (double)b8 + p.nu9_h2 * (double)b9;
     t.c10 = p.nu10_h2 * (double)b10;
@@ -248,18 +264,18 @@ __device__ __forceinline__ int rhs(const DevParams& p, const TConst& c, const do
 
     // eq. 2 assembly
     const R Dr = (R)D;
-#define ADM1_IN(k) (Dr * ((R)sin[state_row(k)] - (R)y[k]))
-    f[Ssu] = (double)(ADM1_IN(Ssu) + rho[1] + (R)(1.0 - p.f_fa_li) * rho[3] - rho[4]);
-    f[Saa] = (double)(ADM1_IN(Saa) + rho[2] - rho[5]);
-    f[Sfa] = (double)(ADM1_IN(Sfa) + (R)p.f_fa_li * rho[3] - rho[6]);
-    f[Sva] = (double)(ADM1_IN(Sva) + (R)p.nu6_va * rho[5] - rho[7]);
-    f[Sbu] = (double)(ADM1_IN(Sbu) + (R)p.nu5_bu * rho[4] + (R)p.nu6_bu * rho[5] - rho[8]);
-    f[Spro] = (double)(ADM1_IN(Spro) + (R)p.nu5_pro * rho[4] + (R)p.nu6_pro * rho[5] +
-                       (R)p.nu8_pro * rho[7] - rho[9]);
-    f[Sac] = (double)(ADM1_IN(Sac) + (R)p.nu5_ac * rho[4] + (R)p.nu6_ac * rho[5] +
+#define ADM1_IN(k) ((R)inflow(state_row(k)) - Dr * (R)y[k])
+    out(Ssu, (double)(ADM1_IN(Ssu) + rho[1] + (R)(1.0 - p.f_fa_li) * rho[3] - rho[4]));
+    out(Saa, (double)(ADM1_IN(Saa) + rho[2] - rho[5]));
+    out(Sfa, (double)(ADM1_IN(Sfa) + (R)p.f_fa_li * rho[3] - rho[6]));
+    out(Sva, (double)(ADM1_IN(Sva) + (R)p.nu6_va * rho[5] - rho[7]));
+    out(Sbu, (double)(ADM1_IN(Sbu) + (R)p.nu5_bu * rho[4] + (R)p.nu6_bu * rho[5] - rho[8]));
+    out(Spro, (double)(ADM1_IN(Spro) + (R)p.nu5_pro * rho[4] + (R)p.nu6_pro * rho[5] +
+                       (R)p.nu8_pro * rho[7] - rho[9]));
+    out(Sac, (double)(ADM1_IN(Sac) + (R)p.nu5_ac * rho[4] + (R)p.nu6_ac * rho[5] +
                       (R)p.nu7_ac * rho[6] + (R)p.nu8_ac * rho[7] + (R)p.nu9_ac * rho[8] +
-                      (R)p.nu10_ac * rho[9] - rho[10]);
-    f[Sch4] = (double)(ADM1_IN(Sch4) + (R)p.nu11_ch4 * rho[10] + (R)p.nu12_ch4 * rho[11] - T9);
+                      (R)p.nu10_ac * rho[9] - rho[10]));
+    out(Sch4, (double)(ADM1_IN(Sch4) + (R)p.nu11_ch4 * rho[10] + (R)p.nu12_ch4 * rho[11] - T9));
     {
         R sic = ADM1_IN(SIC) - T10, sin_ = ADM1_IN(SIN);
 #pragma unroll
@@ -267,38 +283,48 @@ __device__ __forceinline__ int rhs(const DevParams& p, const TConst& c, const do
             sic += (R)p.nuIC[j] * rho[j];
             sin_ += (R)p.nuIN[j] * rho[j];
         }
-        f[SIC] = (double)sic;
-        f[SIN] = (double)sin_;
+        out(SIC, (double)sic);
+        out(SIN, (double)sin_);
     }
-    f[SI] = (double)(ADM1_IN(SI) + (R)p.f_sI_xc * rho[0]);
-    f[Xxc] = (double)(ADM1_IN(Xxc) - rho[0] + rho[12] + rho[13] + rho[14] + rho[15] + rho[16] +
-                      rho[17] + rho[18]);
-    f[Xch] = (double)(ADM1_IN(Xch) + (R)p.f_ch_xc * rho[0] - rho[1]);
-    f[Xpr] = (double)(ADM1_IN(Xpr) + (R)p.f_pr_xc * rho[0] - rho[2]);
-    f[Xli] = (double)(ADM1_IN(Xli) + (R)p.f_li_xc * rho[0] - rho[3]);
-    f[Xsu] = (double)(ADM1_IN(Xsu) + (R)p.Y_su * rho[4] - rho[12]);
-    f[Xaa] = (double)(ADM1_IN(Xaa) + (R)p.Y_aa * rho[5] - rho[13]);
-    f[Xfa] = (double)(ADM1_IN(Xfa) + (R)p.Y_fa * rho[6] - rho[14]);
-    f[Xc4] = (double)(ADM1_IN(Xc4) + (R)p.Y_c4 * (rho[7] + rho[8]) - rho[15]);
-    f[Xpro] = (double)(ADM1_IN(Xpro) + (R)p.Y_pro * rho[9] - rho[16]);
-    f[Xac] = (double)(ADM1_IN(Xac) + (R)p.Y_ac * rho[10] - rho[17]);
-    f[Xh2] = (double)(ADM1_IN(Xh2) + (R)p.Y_h2 * rho[11] - rho[18]);
-    f[XI] = (double)(ADM1_IN(XI) + (R)p.f_xI_xc * rho[0]);
-    f[Scat] = (double)ADM1_IN(Scat);
-    f[San] = (double)ADM1_IN(San);
+    out(SI, (double)(ADM1_IN(SI) + (R)p.f_sI_xc * rho[0]));
+    out(Xxc, (double)(ADM1_IN(Xxc) - rho[0] + rho[12] + rho[13] + rho[14] + rho[15] + rho[16] +
+                      rho[17] + rho[18]));
+    out(Xch, (double)(ADM1_IN(Xch) + (R)p.f_ch_xc * rho[0] - rho[1]));
+    out(Xpr, (double)(ADM1_IN(Xpr) + (R)p.f_pr_xc * rho[0] - rho[2]));
+    out(Xli, (double)(ADM1_IN(Xli) + (R)p.f_li_xc * rho[0] - rho[3]));
+    out(Xsu, (double)(ADM1_IN(Xsu) + (R)p.Y_su * rho[4] - rho[12]));
+    out(Xaa, (double)(ADM1_IN(Xaa) + (R)p.Y_aa * rho[5] - rho[13]));
+    out(Xfa, (double)(ADM1_IN(Xfa) + (R)p.Y_fa * rho[6] - rho[14]));
+    out(Xc4, (double)(ADM1_IN(Xc4) + (R)p.Y_c4 * (rho[7] + rho[8]) - rho[15]));
+    out(Xpro, (double)(ADM1_IN(Xpro) + (R)p.Y_pro * rho[9] - rho[16]));
+    out(Xac, (double)(ADM1_IN(Xac) + (R)p.Y_ac * rho[10] - rho[17]));
+    out(Xh2, (double)(ADM1_IN(Xh2) + (R)p.Y_h2 * rho[11] - rho[18]));
+    out(XI, (double)(ADM1_IN(XI) + (R)p.f_xI_xc * rho[0]));
+    out(Scat, (double)ADM1_IN(Scat));
+    out(San, (double)ADM1_IN(San));
 #undef ADM1_IN
     const R ivg = (R)p.inv_vg;
-    f[Gh2] = (double)((T8 - q * (R)y[Gh2]) * ivg);
-    f[Gch4] = (double)((T9 - q * (R)y[Gch4]) * ivg);
-    f[Gco2] = (double)((T10 - q * (R)y[Gco2]) * ivg);
+    out(Gh2, (double)((T8 - q * (R)y[Gh2]) * ivg));
+    out(Gch4, (double)((T9 - q * (R)y[Gch4]) * ivg));
+    out(Gco2, (double)((T10 - q * (R)y[Gco2]) * ivg));
     return 0;
+}
+
+template <typename R>
+__device__ __forceinline__ int rhs(const DevParams& p, const TConst& c, const double* y,
+                                   double D, const double* sin, double& H, double& Sh2,
+                                   double* f, int& iters)
+{
+    return rhs_in<R>(p, c, y, D, FeedInflow{D, sin}, H, Sh2,
+                     [f](int k, double v) { f[k] = v; }, iters);
 }
 
 // ---------------------------------------------------------------------------
 // Analytic partial derivatives of every rate in its inputs, at fixed
 // (S_H+, S_h2), for the bordered Newton matrix.  FP64.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void partials(const DevParams& p, const TConst& c, const double* y,
+template <typename Y>
+__device__ __forceinline__ void partials(const DevParams& p, const TConst& c, const Y& y,
                                          double H, double S, Partials& d)
 {
     const double a = c.arr;

@@ -38,7 +38,7 @@ __device__ __forceinline__ double step_factor(double err)
 {
     if (!(err < INFINITY)) return 0.2;
     if (err == 0.0) return 5.0;
-    return fmin(5.0, fmax(0.2, 0.9 * pow(err, -0.25)));
+    return fmin(5.0, fmax(0.2, 0.9 / sqrt(sqrt(err))));
 }
 
 }  // namespace adm1

@@ -274,7 +274,204 @@ def emit_sparse1():
     return "\n".join(out) + "\n"
 
 
+def pairing(order, cur):
+    """Rows (elimination positions) paired over the two lanes of a particle.
+    The two constraint rows form the last pair; the others are paired greedily,
+    longest pattern first, with the partner adding the fewest new columns."""
+    pos = {v: p for p, v in enumerate(order)}
+    rows = {p: set() for p in range(NV)}
+    for (r, c) in cur:
+        rows[pos[r]].add(pos[c])
+    pairs = []
+    remaining = list(range(NV - 2))
+    while remaining:
+        a = max(remaining, key=lambda q: (len(rows[q]), -q))
+        remaining.remove(a)
+        b = min(remaining, key=lambda q: (len(rows[a] | rows[q]) - len(rows[a]),
+                                          -len(rows[q]), q))
+        remaining.remove(b)
+        pairs.append((min(a, b), max(a, b)))
+    pairs.sort()
+    pairs.append((NV - 2, NV - 1))
+    return pairs, rows
+
+
+def emit_sparse2():
+    """Two lanes per particle.  Lane side h of pair m owns the row at
+    elimination position pairs[m][h]; register w<m>_<c> holds, on each lane,
+    its own row's entry in column position c (the union of the two rows'
+    patterns, absent entries being zero).  `odd` is the lane side.  Pivot
+    rows and solution components move between the two lanes with DPP
+    broadcasts (bc<h>), so both lanes run the same instruction stream."""
+    order, cur, L, U = analyze()
+    M = entries()
+    pos = {v: p for p, v in enumerate(order)}
+    pairs, rows = pairing(order, cur)
+    side = {}
+    pair_of = {}
+    for m, (a, b) in enumerate(pairs):
+        side[a], side[b] = 0, 1
+        pair_of[a], pair_of[b] = m, m
+    slots = {m: sorted(rows[a] | rows[b]) for m, (a, b) in enumerate(pairs)}
+    var = lambda p: order[p]  # noqa: E731
+    out = ["// Generated by gen_jac.py: two-lanes-per-particle sparse bordered LU.",
+           f"// pairs (elimination positions): {pairs}",
+           f"// slots per lane: {sum(len(s) for s in slots.values())}"]
+
+    def cexpr(p, c):
+        r, cv = var(p), var(c)
+        if (r, cv) in M:
+            e = expr(M[(r, cv)], cv)
+            return e.replace("(alpha + D)", "(alpha + D)")
+        return "0.0"
+
+    # declarations
+    decl = []
+    for m in range(len(pairs)):
+        decl += [f"w{m}_{c}" for c in slots[m]]
+    out.append("#define ADM1_SP2_DECL \\")
+    for k in range(0, len(decl), 10):
+        out.append("    double " + ", ".join(decl[k:k + 10]) + "; \\")
+    out.append("    (void)0")
+    # assembly
+    out.append("#define ADM1_SP2_BUILD(alpha, D) \\")
+    for m, (a, b) in enumerate(pairs):
+        for c in slots[m]:
+            e0, e1 = cexpr(a, c), cexpr(b, c)
+            if e0 == e1:
+                out.append(f"    w{m}_{c} = {e0}; \\")
+            else:
+                out.append(f"    w{m}_{c} = odd ? ({e1}) : ({e0}); \\")
+    out.append("    (void)0")
+
+    def role(q, k, structural):
+        if q == k:
+            return "P"
+        if q < k:
+            return "U"
+        return "L" if structural else "Z"
+
+    def roles(m, k):
+        a, b = pairs[m]
+        return (role(a, k, (var(a), var(k)) in cur), role(b, k, (var(b), var(k)) in cur))
+
+    def masked(m, k, want):
+        """Expression of slot (m, k) restricted to lanes whose role is in want
+        ({'L','Z'} for the forward direction, {'U'} for the backward one)."""
+        r = roles(m, k)
+        ok = [x in want for x in r]
+        if all(ok):
+            return f"w{m}_{k}"
+        if not any(ok):
+            return None
+        h = 0 if ok[0] else 1
+        return f"({'odd' if h else '!odd'} ? w{m}_{k} : 0.0)"
+
+    counts = dict(bcast=0, fma_factor=0, fma_solve=0, sel=0)
+    # factorisation
+    out.append("#define ADM1_SP2_FACTOR(ok) \\")
+    for k in range(NV):
+        mk, sk = pair_of[k], side[k]
+        out.append(f"    {{ const double iv = bc{sk}(1.0 / w{mk}_{k}); ok = ok && isfinite(iv); \\")
+        counts["bcast"] += 1
+        lpairs = []
+        for m in range(len(pairs)):
+            if k not in slots[m]:
+                continue
+            r0, r1 = roles(m, k)
+            rr = (r0, r1)
+            if "P" in rr:
+                other = r1 if r0 == "P" else r0
+                ps = 0 if r0 == "P" else 1
+                pick = "odd" if ps == 1 else "!odd"
+                if other in ("L", "Z"):
+                    out.append(f"      w{m}_{k} = {pick} ? iv : w{m}_{k} * iv; \\")
+                else:
+                    out.append(f"      w{m}_{k} = {pick} ? iv : w{m}_{k}; \\")
+                counts["sel"] += 1
+                if other == "L":
+                    lpairs.append(m)
+            elif r0 in ("L", "Z") and r1 in ("L", "Z"):
+                if "L" in rr:
+                    out.append(f"      w{m}_{k} *= iv; \\")
+                    lpairs.append(m)
+            elif "L" in rr:
+                h = 0 if r0 == "L" else 1
+                pick = "odd" if h == 1 else "!odd"
+                out.append(f"      w{m}_{k} = {pick} ? w{m}_{k} * iv : w{m}_{k}; \\")
+                counts["sel"] += 1
+                lpairs.append(m)
+        if lpairs and U[var(k)]:
+            ucols = [pos[j] for j in U[var(k)]]
+            for c in ucols:
+                out.append(f"      const double u{c} = bc{sk}(w{mk}_{c}); \\")
+                counts["bcast"] += 1
+            for m in lpairs:
+                lx = masked(m, k, {"L", "Z"})
+                out.append(f"      {{ const double l = {lx}; \\")
+                for c in ucols:
+                    if c in slots[m]:
+                        out.append(f"        w{m}_{c} -= l * u{c}; \\")
+                        counts["fma_factor"] += 1
+                out.append("      } \\")
+        out.append("    } \\")
+    out.append("    (void)0")
+    # forward / backward substitution on b<m> (own components)
+    out.append("#define ADM1_SP2_SOLVE() \\")
+    for k in range(NV):
+        mk, sk = pair_of[k], side[k]
+        targets = [m for m in range(len(pairs)) if k in slots[m] and masked(m, k, {"L"})
+                   is not None and any(x == "L" for x in roles(m, k))]
+        if not targets:
+            continue
+        out.append(f"    {{ const double z = bc{sk}(b{mk}); \\")
+        counts["bcast"] += 1
+        for m in targets:
+            out.append(f"      b{m} -= {masked(m, k, {'L', 'Z'})} * z; \\")
+            counts["fma_solve"] += 1
+        out.append("    } \\")
+    for k in reversed(range(NV)):
+        mk, sk = pair_of[k], side[k]
+        pick = "odd" if sk == 1 else "!odd"
+        out.append(f"    b{mk} = {pick} ? b{mk} * w{mk}_{k} : b{mk}; \\")
+        counts["sel"] += 1
+        targets = [m for m in range(len(pairs)) if k in slots[m] and
+                   any(x == "U" for x in roles(m, k)) and
+                   (var(pairs[m][0]), var(k)) in cur | {(var(pairs[m][1]), var(k))} | set()]
+        targets = [m for m in range(len(pairs)) if k in slots[m] and
+                   any(roles(m, k)[h] == "U" and (var(pairs[m][h]), var(k)) in cur
+                       for h in (0, 1))]
+        if not targets:
+            continue
+        out.append(f"    {{ const double x = bc{sk}(b{mk}); \\")
+        counts["bcast"] += 1
+        for m in targets:
+            out.append(f"      b{m} -= {masked(m, k, {'U'})} * x; \\")
+            counts["fma_solve"] += 1
+        out.append("    } \\")
+    out.append("    (void)0")
+    # which pair/side owns each differential variable's row
+    out.append("// owner of each variable's row: pair and side")
+    own_pair = [pair_of[pos[v]] for v in range(NV)]
+    own_side = [side[pos[v]] for v in range(NV)]
+    out.append(f"#define ADM1_SP2_NPAIR {len(pairs)}")
+    out.append("#define ADM1_SP2_VAR_PAIR {" + ", ".join(map(str, own_pair)) + "}")
+    out.append("#define ADM1_SP2_VAR_SIDE {" + ", ".join(map(str, own_side)) + "}")
+    # variable held by side h of pair m
+    pv0 = [var(a) for a, b in pairs]
+    pv1 = [var(b) for a, b in pairs]
+    out.append("#define ADM1_SP2_PAIR_VAR0 {" + ", ".join(map(str, pv0)) + "}")
+    out.append("#define ADM1_SP2_PAIR_VAR1 {" + ", ".join(map(str, pv1)) + "}")
+    out.append(f"// counts per lane: {counts}")
+    return "\n".join(out) + "\n", counts, sum(len(s) for s in slots.values())
+
+
 def main():
+    with open(os.path.join(HERE, "adm1_jac_sparse2.inc"), "w") as fh:
+        txt, counts, nslots = emit_sparse2()
+        fh.write(txt)
+    if "--stats" in sys.argv:
+        print("sparse2 slots/lane", nslots, counts)
     with open(os.path.join(HERE, "adm1_partials.inc"), "w") as fh:
         fh.write("// Generated by gen_jac.py -- do not edit.\n" + emit_partials_struct() + "\n")
     with open(os.path.join(HERE, "adm1_jac_dense.inc"), "w") as fh:
