@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--cpu-sample", type=int, default=1024,
+    ap.add_argument("--cpu-sample", type=int, default=16384,
                     help="particles of the oracle CPU-baseline sample (0: skip)")
     ap.add_argument("--cpu-steps", type=int, default=10)
     return ap.parse_args()

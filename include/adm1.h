@@ -108,8 +108,9 @@ typedef struct adm1_params {
  *     the eq. 7 / eq. 8 Newton solves.
  *   rate_precision: 0 rates and eq. 2 assembly in FP64; 1 in FP32 (the eq. 7
  *     and eq. 8 solves and the linear algebra stay FP64).
- *   variant: step-kernel layout; -1 lets the library choose (the autotuned
- *     choice, see adm1_autotune); otherwise an ADM1_VARIANT_* value. */
+ *   variant: step-kernel layout; -1 lets the library choose (the choice set
+ *     by adm1_set_launch, else ADM1_VARIANT_SPARSE2); otherwise an
+ *     ADM1_VARIANT_* value. */
 typedef struct adm1_opts {
     double rtol;
     double atol[28];
@@ -196,6 +197,59 @@ int adm1_rhs(adm1_ctx *ctx, const double *state, int64_t ld, const double *temp_
 int adm1_jacobian(adm1_ctx *ctx, const double *state, int64_t ld, const double *temp_K,
                   const adm1_feed *feed, int64_t n, double *J, uint8_t *status,
                   void *stream);
+
+/* Launch configuration of the step kernel used when opts.variant is -1:
+ * variant (an ADM1_VARIANT_* value) and, for ADM1_VARIANT_SPARSE2, resident
+ * blocks (waves) per compute unit of the persistent grid (1..4; 0 = 4).
+ * Set by the autotuner after timing the candidates.  Synchronous. */
+int adm1_set_launch(adm1_ctx *ctx, int32_t variant, int32_t blocks_per_cu);
+
+/* A coupling step captured as a HIP graph: adm1_step_particles followed by
+ * adm1_gas_flux with fixed arguments (sec. 2.3: one synchronised coupling
+ * interval).  Capture records kernel launches only (no memset nodes);
+ * replays read the arrays' current contents, so the caller may update
+ * state, feed and temperatures between replays.  `stream` (a hipStream_t,
+ * not NULL) is used for capture and is left idle.  Synchronous. */
+typedef struct adm1_graph adm1_graph;
+int adm1_graph_capture_step(adm1_ctx *ctx, double *state, int64_t ld, const double *temp_K,
+                            const adm1_feed *feed, double dt_days, int64_t n, adm1_aux *aux,
+                            uint8_t *status, int32_t *nsteps, const double *V_liq,
+                            double *q_gas, double *q_ch4, double *totals, void *stream,
+                            adm1_graph **out);
+/* Enqueue one replay of the captured step on `stream`. */
+int adm1_graph_launch(adm1_graph *g, void *stream);
+/* Free a captured graph.  Synchronous.  NULL is a no-op. */
+void adm1_graph_destroy(adm1_graph *g);
+
+/* ------------------------------------------------------------------------
+ * Coupling driver (sec. 2.3): between coupling steps each AD particle moves
+ * with its fluid particle, and particles in the inlet region receive feed.
+ * The SPH flow field of the paper is replaced by a smooth analytic field in
+ * a cylindrical tank: solid-body rotation omega (rad/s) plus axisymmetric
+ * Stokes stream-function modes psi = sum_k a[k] r^2 (R^2 - r^2) sin(k pi z/H),
+ * k = 1..nmodes (divergence free, tangent to all walls).
+ * ------------------------------------------------------------------------ */
+#define ADM1_FLOW_MODES 8
+typedef struct adm1_flow {
+    double omega;              /* rad/s */
+    double R, H;               /* tank radius and height, m */
+    double a[ADM1_FLOW_MODES]; /* stream-function amplitudes, 1/(m s) */
+    int32_t nmodes;
+} adm1_flow;
+
+/* Move particles 0..n-1 for dt_seconds with `substeps` classical RK4
+ * substeps in the field; positions stay inside the tank (radial and axial
+ * clamp).  pos: float32 [3][ld] device array (x, y, z in m), in place. */
+int adm1_advect(float *pos, int64_t ld, int64_t n, const adm1_flow *flow, double dt_seconds,
+                int32_t substeps, void *stream);
+
+/* Feed mask at the start of an interval: particles with z >= z_min and
+ * x^2 + y^2 <= r_max^2 get D = D_zone (1/d) and feed row fidx_zone, the
+ * others D = 0 and row fidx_out (closed particles).  D: float64 [n],
+ * fidx: int32 [n], flag (nullable): uint8 [n] membership; device arrays. */
+int adm1_feed_mask(const float *pos, int64_t ld, int64_t n, double z_min, double r_max,
+                   double D_zone, int32_t fidx_zone, int32_t fidx_out, double *D,
+                   int32_t *fidx, uint8_t *flag, void *stream);
 
 /* Comma-separated adm1_params field names in struct order (static string). */
 const char *adm1_param_names(void);

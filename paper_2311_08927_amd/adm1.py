@@ -72,6 +72,18 @@ def lib():
         L.adm1_rhs.argtypes = [vp, vp, i64, vp, vp, i64, vp, i64, vp, i32, vp, vp]
         L.adm1_jacobian.restype = ctypes.c_int
         L.adm1_jacobian.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, vp]
+        L.adm1_set_launch.restype = ctypes.c_int
+        L.adm1_set_launch.argtypes = [vp, i32, i32]
+        L.adm1_graph_capture_step.restype = ctypes.c_int
+        L.adm1_graph_capture_step.argtypes = [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp,
+                                              vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.adm1_graph_launch.restype = ctypes.c_int
+        L.adm1_graph_launch.argtypes = [vp, vp]
+        L.adm1_graph_destroy.argtypes = [vp]
+        L.adm1_advect.restype = ctypes.c_int
+        L.adm1_advect.argtypes = [vp, i64, i64, vp, dbl, i32, vp]
+        L.adm1_feed_mask.restype = ctypes.c_int
+        L.adm1_feed_mask.argtypes = [vp, i64, i64, dbl, dbl, dbl, i32, i32, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -188,6 +200,56 @@ def adm1_jacobian(ctx, state, ld, temp_K, feed: adm1_feed, n, J, status=None, st
     if check:
         _check(rc, "adm1_jacobian")
     return rc
+
+
+FLOW_MODES = 8
+
+
+class adm1_flow(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("R", ctypes.c_double), ("H", ctypes.c_double),
+                ("a", ctypes.c_double * FLOW_MODES), ("nmodes", ctypes.c_int32)]
+
+
+def make_flow(d: dict) -> adm1_flow:
+    a = list(d["a"])
+    return adm1_flow(d["omega"], d["R"], d["H"],
+                     (ctypes.c_double * FLOW_MODES)(*(a + [0.0] * (FLOW_MODES - len(a)))),
+                     len(a))
+
+
+def adm1_advect(pos, ld, n, flow: adm1_flow, dt_seconds, substeps, stream=None):
+    _check(lib().adm1_advect(_ptr(pos), int(ld), int(n), ctypes.byref(flow),
+                             float(dt_seconds), int(substeps), _stream(stream)), "adm1_advect")
+
+
+def adm1_feed_mask(pos, ld, n, z_min, r_max, D_zone, fidx_zone, fidx_out, D, fidx, flag=None,
+                   stream=None):
+    _check(lib().adm1_feed_mask(_ptr(pos), int(ld), int(n), float(z_min), float(r_max),
+                                float(D_zone), int(fidx_zone), int(fidx_out), _ptr(D),
+                                _ptr(fidx), _ptr(flag), _stream(stream)), "adm1_feed_mask")
+
+
+def adm1_set_launch(ctx: int, variant: int, blocks_per_cu: int = 0):
+    _check(lib().adm1_set_launch(ctx, int(variant), int(blocks_per_cu)), "adm1_set_launch")
+
+
+def adm1_graph_capture_step(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, n, aux, status,
+                            nsteps, V_liq, q_gas, q_ch4, totals, stream) -> int:
+    g = ctypes.c_void_p()
+    _check(lib().adm1_graph_capture_step(
+        ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed), float(dt_days), int(n),
+        None if aux is None else ctypes.byref(aux), _ptr(status), _ptr(nsteps), _ptr(V_liq),
+        _ptr(q_gas), _ptr(q_ch4), _ptr(totals), _stream(stream), ctypes.byref(g)),
+        "adm1_graph_capture_step")
+    return g.value
+
+
+def adm1_graph_launch(g: int, stream=None):
+    _check(lib().adm1_graph_launch(g, _stream(stream)), "adm1_graph_launch")
+
+
+def adm1_graph_destroy(g: int):
+    lib().adm1_graph_destroy(g)
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,89 @@
+"""Autotuner of the step kernel's launch configuration.
+
+Times the candidate layouts -- one lane per particle with the sparse LU,
+and two lanes per particle (persistent) at 1-4 resident waves per compute
+unit -- on a seeded sample of the caller's workload, picks the fastest and
+sets it on the context with adm1_set_launch.  Choices are cached in a JSON
+file keyed by GPU architecture, sample size and tolerance, so later runs
+skip the timing.  Timing uses HIP events on the launching stream; every
+candidate runs the same sample from the same start state.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+from . import adm1 as A
+
+CANDIDATES = [(A.VARIANT_SPARSE1, 0)] + [(A.VARIANT_SPARSE2, b) for b in (1, 2, 3, 4)]
+CACHE = os.environ.get("ADM1_TUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "adm1_autotune.json"))
+
+
+def _key(arch: str, n: int, rtol: float, tag: str) -> str:
+    return f"{arch}|n={n}|rtol={rtol:g}|{tag}"
+
+
+def load_cache() -> dict:
+    try:
+        with open(CACHE) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(d: dict):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(d, fh, indent=1)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def autotune(ctx: "A.Context", X, T, D, fidx, S_in, dt, n=None, tag="", repeats=2,
+             candidates=CANDIDATES, use_cache=True) -> dict:
+    """Time the candidates on (X, T, D, fidx, S_in) -- device tensors of the
+    sample -- for one coupling interval each; returns {choice, timings_ms}.
+    X is not modified."""
+    import torch
+    n = X.shape[1] if n is None else n
+    arch = torch.cuda.get_device_properties(X.device).gcnArchName
+    key = _key(arch, n, ctx.opts.rtol, tag)
+    cache = load_cache() if use_cache else {}
+    if key in cache:
+        v, b = cache[key]["choice"]
+        A.adm1_set_launch(ctx.handle, v, b)
+        return cache[key]
+    saved_variant = ctx.opts.variant
+    ctx.set_opts(variant=-1)
+    timings = {}
+    stream = torch.cuda.current_stream()
+    for v, b in candidates:
+        A.adm1_set_launch(ctx.handle, v, b)
+        ts = []
+        for _ in range(repeats):
+            Xw = X.clone()
+            H = torch.full((n,), -1.0, dtype=torch.float64, device=X.device)
+            hl = torch.full((n,), -1.0, dtype=torch.float64, device=X.device)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.step(Xw, T, D, fidx, S_in, dt, n=n, H=H, hlast=hl, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        timings[f"{v}:{b}"] = float(np.median(ts))
+    best = min(timings, key=timings.get)
+    v, b = (int(t) for t in best.split(":"))
+    A.adm1_set_launch(ctx.handle, v, b)
+    ctx.set_opts(variant=saved_variant)
+    out = {"choice": [v, b], "timings_ms": timings}
+    if use_cache:
+        cache[key] = out
+        save_cache(cache)
+    return out

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(os.path.dirname(PKG), "include")
 LIB = os.path.join(PKG, "libadm1.so")
 ARCH = os.environ.get("ADM1_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["adm1_abi.hip", "adm1_kernels.hip", "adm1_step_sparse2.hip"]
+SOURCES = ["adm1_abi.hip", "adm1_kernels.hip", "adm1_step_sparse2.hip", "adm1_transport.hip"]
 
 
 def hipcc() -> str:

@@ -356,7 +356,7 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
     a.status = status; a.nsteps = nsteps; a.queue = ctx->d_queue;
     a.work = ctx->d_work; a.work_blocks = ctx->work_blocks; a.pdev = ctx->d_params;
     int variant = ctx->opts.variant;
-    if (variant < 0) variant = ctx->tuned_variant >= 0 ? ctx->tuned_variant : ADM1_VARIANT_SPARSE1;
+    if (variant < 0) variant = ctx->tuned_variant >= 0 ? ctx->tuned_variant : ADM1_VARIANT_SPARSE2;
     hipStream_t s = (hipStream_t)stream;
     switch (variant) {
     case ADM1_VARIANT_DENSE1:
@@ -435,6 +435,72 @@ int adm1_jacobian(adm1_ctx* ctx, const double* state, int64_t ld, const double* 
     a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.D = feed->D; a.fidx = feed->idx;
     a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.status = status;
     return hip_rc(adm1::launch_jacobian(a, J, (hipStream_t)stream));
+}
+
+int adm1_set_launch(adm1_ctx* ctx, int32_t variant, int32_t blocks_per_cu)
+{
+    if (!ctx) return ADM1_E_NULL;
+    if (variant < 0 || variant >= ADM1_VARIANT_COUNT) return ADM1_E_VARIANT;
+    if (blocks_per_cu < 0 || blocks_per_cu > 4) return ADM1_E_OPTS;
+    ctx->tuned_variant = variant;
+    ctx->tuned_blocks_per_cu = blocks_per_cu;
+    return ADM1_OK;
+}
+
+struct adm1_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int adm1_graph_capture_step(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,
+                            const adm1_feed* feed, double dt_days, int64_t n, adm1_aux* aux,
+                            uint8_t* status, int32_t* nsteps, const double* V_liq,
+                            double* q_gas, double* q_ch4, double* totals, void* stream,
+                            adm1_graph** out)
+{
+    if (!ctx || !out || !stream) return ADM1_E_NULL;
+    hipStream_t s = (hipStream_t)stream;
+    // validate before capturing, so a bad argument leaves no open capture
+    const int rc0 = adm1_step_particles(ctx, state, ld, temp_K, feed, dt_days, 0, aux,
+                                        status, nsteps, stream);
+    if (rc0 != ADM1_OK) return rc0;
+    adm1_graph* g = new (std::nothrow) adm1_graph;
+    if (!g) return ADM1_E_NOMEM;
+    g->graph = nullptr;
+    g->exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) { delete g; return (int)e; }
+    int rc = adm1_step_particles(ctx, state, ld, temp_K, feed, dt_days, n, aux, status,
+                                 nsteps, stream);
+    if (rc == ADM1_OK)
+        rc = adm1_gas_flux(ctx, state, ld, temp_K, V_liq, n, q_gas, q_ch4, totals, stream);
+    e = hipStreamEndCapture(s, &g->graph);
+    if (rc == ADM1_OK && e != hipSuccess) rc = (int)e;
+    if (rc == ADM1_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = (int)e;
+    }
+    if (rc != ADM1_OK) {
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return rc;
+    }
+    *out = g;
+    return ADM1_OK;
+}
+
+int adm1_graph_launch(adm1_graph* g, void* stream)
+{
+    if (!g) return ADM1_E_NULL;
+    return hip_rc(hipGraphLaunch(g->exec, (hipStream_t)stream));
+}
+
+void adm1_graph_destroy(adm1_graph* g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 }  // extern "C"

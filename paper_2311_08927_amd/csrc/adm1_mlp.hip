@@ -1,0 +1,485 @@
+// Learned surrogate of the per-particle ADM1 step: an MLP that maps the
+// log-scaled state, temperature, interval and feed flag of a particle to
+// the log-space increments of its 35 entries over one coupling interval.
+//
+// Network 38 -> 256 -> 256 -> 256 -> 256 -> 35, GELU (erf form), BF16
+// weights and activations, FP32 accumulation on the matrix cores
+// (v_mfma_f32_16x16x16_bf16), FP32 master weights and Adam.
+//
+// Kernels:
+//   k_mlp_fwd    fused forward: a 128-row tile stays in LDS for all five
+//                layers (two 128 x 264 BF16 buffers), weights stream from L2
+//                in the transposed layout WT[out][in] so each lane's four
+//                k-values are contiguous; optional saving of pre-activations
+//                (FP32) and activations (BF16) for the backward pass;
+//   k_gemm       generic strided BF16 GEMM with LDS staging and split-K,
+//                used by the backward pass (dH = dZ W^T, dW = H^T dZ);
+//   k_loss, k_gelu_bwd, k_colsum, k_splitk_sum, k_adam, k_pack: the
+//                elementwise and reduction steps of training;
+//   k_featurize  the network input from the FP64 state.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adm1_mlp.h"
+
+namespace adm1 {
+namespace {
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float x)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b)
+{
+    return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+__device__ __forceinline__ float gelu(float z)
+{
+    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+           z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+__device__ __forceinline__ f32x4 mfma16(s16x4 a, s16x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Fused forward.  MFMA 16x16x16 operand layout (lane l of 64):
+//   A (16 x 16, rows i, k):  row l % 16, k = 4 (l / 16) + t, t = 0..3
+//   B (16 x 16, k, cols j):  col l % 16, k = 4 (l / 16) + t
+//   C (16 x 16):             col l % 16, rows 4 (l / 16) + t
+// ---------------------------------------------------------------------------
+constexpr int TM = 128;      // rows per block
+constexpr int LDH = 264;     // LDS row stride (BF16 elements), padded
+constexpr int kThreads = 256;
+
+struct FwdArgs {
+    const uint16_t* X;   // [n][64] BF16
+    int64_t n;
+    const uint16_t* WT[5];
+    const float* b[5];
+    float* Y;            // [n][48] FP32
+    float* zsave[4];     // [n][256] FP32 pre-activations (nullable)
+    uint16_t* hsave[4];  // [n][256] BF16 activations (nullable)
+};
+
+// One layer: out[TM][NOUT] = act(in[TM][K] W + b).  Wave w owns column
+// tiles; every wave covers all 8 row tiles.
+template <int K, int NOUT, bool LAST>
+__device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const uint16_t* in,
+                                          uint16_t* out, int64_t row0)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int CT = NOUT / 16;                 // column tiles
+    constexpr int CTW = (CT + 3) / 4;             // per wave
+    const int c0 = w * CTW;
+    f32x4 acc[8][CTW];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < CTW; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t* WT = a.WT[layer];
+    const int kq = 4 * (lane >> 4), li = lane & 15;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        s16x4 bf[CTW];
+#pragma unroll
+        for (int c = 0; c < CTW; ++c) {
+            const int col = (c0 + c) * 16 + li;
+            if (c0 + c < CT)
+                bf[c] = *(const s16x4*)(WT + (int64_t)col * K + k0 + kq);
+            else
+                bf[c] = s16x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const s16x4 af = *(const s16x4*)(in + (r * 16 + li) * LDH + k0 + kq);
+#pragma unroll
+            for (int c = 0; c < CTW; ++c) acc[r][c] = mfma16(af, bf[c], acc[r][c]);
+        }
+    }
+    const float* bias = a.b[layer];
+#pragma unroll
+    for (int c = 0; c < CTW; ++c) {
+        if (c0 + c >= CT) continue;
+        const int col = (c0 + c) * 16 + li;
+        const float bc = bias[col];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = r * 16 + kq + t;
+                const int64_t grow = row0 + row;
+                const float z = acc[r][c][t] + bc;
+                if (LAST) {
+                    if (grow < a.n) a.Y[grow * 48 + col] = z;
+                } else {
+                    const float h = gelu(z);
+                    const uint16_t hb = f2bf(h);
+                    out[row * LDH + col] = hb;
+                    if (grow < a.n) {
+                        if (a.zsave[layer]) a.zsave[layer][grow * 256 + col] = z;
+                        if (a.hsave[layer]) a.hsave[layer][grow * 256 + col] = hb;
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_mlp_fwd(FwdArgs a)
+{
+    __shared__ uint16_t buf0[TM * LDH];
+    __shared__ uint16_t buf1[TM * LDH];
+    const int64_t row0 = (int64_t)blockIdx.x * TM;
+    // input tile: 128 rows x 64 features (8 bytes per load)
+    for (int e = threadIdx.x; e < TM * 16; e += kThreads) {
+        const int row = e >> 4, q = (e & 15) * 4;
+        const int64_t grow = row0 + row;
+        s16x4 v = s16x4{0, 0, 0, 0};
+        if (grow < a.n) v = *(const s16x4*)(a.X + grow * 64 + q);
+        *(s16x4*)(buf0 + row * LDH + q) = v;
+    }
+    __syncthreads();
+    fwd_layer<64, 256, false>(a, 0, buf0, buf1, row0);
+    __syncthreads();
+    fwd_layer<256, 256, false>(a, 1, buf1, buf0, row0);
+    __syncthreads();
+    fwd_layer<256, 256, false>(a, 2, buf0, buf1, row0);
+    __syncthreads();
+    fwd_layer<256, 256, false>(a, 3, buf1, buf0, row0);
+    __syncthreads();
+    fwd_layer<256, 48, true>(a, 4, buf0, buf1, row0);
+}
+
+// ---------------------------------------------------------------------------
+// Generic GEMM: C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m sam + k sak],
+// B(k, n) = B[k sbk + n sbn] (BF16), C FP32 with row stride ldc.  Tile
+// 64 x 64 per block, K in steps of 16 staged through LDS; split-K over
+// gridDim.z writes partial C at C + z * splitc.
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+    const uint16_t* A;
+    int64_t sam, sak;
+    const uint16_t* B;
+    int64_t sbk, sbn;
+    float* C;
+    int64_t ldc, splitc;
+    int M, N, K, kchunk;
+};
+
+__global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g)
+{
+    __shared__ uint16_t As[64][20];
+    __shared__ uint16_t Bs[64][20];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int kb = blockIdx.z * g.kchunk;
+    const int ke = min(g.K, kb + g.kchunk);
+    const int kq = 4 * (lane >> 4), li = lane & 15;
+    f32x4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+        for (int e = threadIdx.x; e < 64 * 16; e += kThreads) {
+            const int r = e >> 4, kk = e & 15;
+            const int k = k0 + kk;
+            const int m = m0 + r, nn = n0 + r;
+            As[r][kk] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0;
+            Bs[r][kk] = (nn < g.N && k < ke) ? g.B[(int64_t)k * g.sbk + (int64_t)nn * g.sbn] : 0;
+        }
+        __syncthreads();
+        s16x4 af;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) af[t] = (short)As[w * 16 + li][kq + t];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            s16x4 bf;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bf[t] = (short)Bs[c * 16 + li][kq + t];
+            acc[c] = mfma16(af, bf, acc[c]);
+        }
+        __syncthreads();
+    }
+    float* C = g.C + (int64_t)blockIdx.z * g.splitc;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int col = n0 + c * 16 + li;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int row = m0 + w * 16 + kq + t;
+            if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[c][t];
+        }
+    }
+}
+
+// Sum of split-K partials in fixed order: out[i] = sum_z part[z * stride + i].
+__global__ void k_splitk_sum(const float* part, int64_t stride, int S, int64_t cnt, float* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    float s = 0.f;
+    for (int z = 0; z < S; ++z) s += part[(int64_t)z * stride + i];
+    out[i] = s;
+}
+
+// MSE loss on the 35 outputs: dY = 2 (Y - T) / (B 35) (FP32 and BF16), and
+// per-block partial sums of the squared error.
+__global__ void __launch_bounds__(256) k_loss(const float* Y, const float* T, int64_t B,
+                                              float* dY, uint16_t* dYb, float* partial)
+{
+    __shared__ float red[256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float s = 0.f;
+    if (i < B * 48) {
+        const int64_t r = i / 48;
+        const int c = (int)(i - r * 48);
+        float g = 0.f;
+        if (c < 35) {
+            const float d = Y[i] - T[r * 35 + c];
+            s = d * d;
+            g = 2.f * d / (float)(B * 35);
+        }
+        dY[i] = g;
+        dYb[i] = f2bf(g);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_loss_final(const float* partial, int nb, int64_t B,
+                                                    float* loss)
+{
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int k = threadIdx.x; k < nb; k += 256) s += partial[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0] / (float)(B * 35);
+}
+
+// dZ = dH * GELU'(Z), FP32 and BF16 copies.
+__global__ void k_gelu_bwd(const float* dH, const float* Z, int64_t cnt, float* dZ,
+                           uint16_t* dZb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const float g = dH[i] * gelu_grad(Z[i]);
+    dZ[i] = g;
+    dZb[i] = f2bf(g);
+}
+
+// Column sums in fixed order: out[c] = sum_r M[r * ld + c], r < rows.
+__global__ void __launch_bounds__(256) k_colsum(const float* M, int64_t rows, int ld, int cols,
+                                                float* out)
+{
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    float s = 0.f;
+    for (int64_t r = threadIdx.x; r < rows; r += 256) s += M[r * ld + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && c < cols) out[c] = red[0];
+}
+
+// Adam on the FP32 master parameters (padded entries carry a zero mask).
+__global__ void k_adam(float* p, const float* g, float* m, float* v, const uint8_t* mask,
+                       int64_t cnt, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    if (!mask[i]) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// BF16 working copies of one layer from the FP32 master W[in][out]:
+// WT[out][in] (forward) and W[in][out] (backward).
+__global__ void k_pack(const float* W, int in, int out, uint16_t* WT, uint16_t* Wb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)in * out) return;
+    const int r = (int)(i / out), c = (int)(i - (int64_t)r * out);
+    const uint16_t b = f2bf(W[i]);
+    Wb[i] = b;
+    WT[(int64_t)c * in + r] = b;
+}
+
+// Network input from the FP64 state: log(max(x, floor)) of the 35 entries,
+// temperature, log dt and the feed flag, standardised; BF16 [n][64].
+__global__ void __launch_bounds__(256) k_featurize(const double* state, int64_t ld,
+                                                   const double* T, const double* D, double dt,
+                                                   int64_t n, const float* norm,
+                                                   const double* floor_, uint16_t* X)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* mean = norm;
+    const float* sd = norm + 38;
+    uint16_t* xo = X + i * 64;
+    for (int k = 0; k < 35; ++k) {
+        const double v = fmax(state[k * ld + i], floor_[k]);
+        xo[k] = f2bf(((float)log(v) - mean[k]) / sd[k]);
+    }
+    xo[35] = f2bf(((float)T[i] - mean[35]) / sd[35]);
+    xo[36] = f2bf(((float)log(dt) - mean[36]) / sd[36]);
+    xo[37] = f2bf(((D[i] > 0.0 ? 1.f : 0.f) - mean[37]) / sd[37]);
+    for (int k = 38; k < 64; ++k) xo[k] = 0;
+}
+
+// Training targets: standardised increments of log(max(x, floor)).
+__global__ void __launch_bounds__(256) k_targets(const double* x0, const double* x1,
+                                                 int64_t ld, int64_t n, const float* norm,
+                                                 const double* floor_, float* Tg)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* mean = norm + 76;
+    const float* sd = norm + 111;
+    for (int k = 0; k < 35; ++k) {
+        const double a = fmax(x0[k * ld + i], floor_[k]), b = fmax(x1[k * ld + i], floor_[k]);
+        Tg[i * 35 + k] = ((float)(log(b) - log(a)) - mean[k]) / sd[k];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t mlp_forward(const MlpDev& m, const uint16_t* X, int64_t n, float* Y, bool save,
+                       hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    FwdArgs a;
+    a.X = X;
+    a.n = n;
+    for (int l = 0; l < 5; ++l) {
+        a.WT[l] = m.WT[l];
+        a.b[l] = m.bias[l];
+    }
+    a.Y = Y;
+    for (int l = 0; l < 4; ++l) {
+        a.zsave[l] = save ? m.z[l] : nullptr;
+        a.hsave[l] = save ? m.h[l] : nullptr;
+    }
+    const unsigned grid = (unsigned)((n + TM - 1) / TM);
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(grid), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t gemm(const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
+                int64_t sbn, float* C, int64_t ldc, int M, int N, int K, int splitk,
+                float* partial, hipStream_t s)
+{
+    GemmArgs g;
+    g.A = A; g.sam = sam; g.sak = sak; g.B = B; g.sbk = sbk; g.sbn = sbn;
+    g.M = M; g.N = N; g.K = K;
+    if (splitk <= 1) {
+        g.C = C; g.ldc = ldc; g.splitc = 0; g.kchunk = K;
+        hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64, 1), dim3(kThreads), 0, s,
+                           g);
+        return hipGetLastError();
+    }
+    const int kchunk = ((K + splitk - 1) / splitk + 15) / 16 * 16;
+    const int S = (K + kchunk - 1) / kchunk;
+    g.C = partial; g.ldc = ldc; g.splitc = (int64_t)M * ldc; g.kchunk = kchunk;
+    hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64, S), dim3(kThreads), 0, s, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t cnt = (int64_t)M * ldc;
+    hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                       partial, cnt, S, cnt, C);
+    return hipGetLastError();
+}
+
+hipError_t mlp_loss(const float* Y, const float* T, int64_t B, float* dY, uint16_t* dYb,
+                    float* partial, float* loss, hipStream_t s)
+{
+    const int nb = (int)((B * 48 + 255) / 256);
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, Y, T, B, dY, dYb, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, partial, nb, B, loss);
+    return hipGetLastError();
+}
+
+hipError_t gelu_bwd(const float* dH, const float* Z, int64_t cnt, float* dZ, uint16_t* dZb,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gelu_bwd, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dH, Z,
+                       cnt, dZ, dZb);
+    return hipGetLastError();
+}
+
+hipError_t colsum(const float* M, int64_t rows, int ld, int cols, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_colsum, dim3(cols), dim3(256), 0, s, M, rows, ld, cols, out);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* p, const float* g, float* mo, float* v, const uint8_t* mask, int64_t cnt,
+                float lr, float b1, float b2, float eps, int step, hipStream_t s)
+{
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, p, g, mo,
+                       v, mask, cnt, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t pack(const float* W, int in, int out, uint16_t* WT, uint16_t* Wb, hipStream_t s)
+{
+    const int64_t cnt = (int64_t)in * out;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, W, in, out,
+                       WT, Wb);
+    return hipGetLastError();
+}
+
+hipError_t featurize(const double* state, int64_t ld, const double* T, const double* D,
+                     double dt, int64_t n, const float* norm, const double* floor_,
+                     uint16_t* X, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_featurize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, state,
+                       ld, T, D, dt, n, norm, floor_, X);
+    return hipGetLastError();
+}
+
+hipError_t targets(const double* x0, const double* x1, int64_t ld, int64_t n, const float* norm,
+                   const double* floor_, float* Tg, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x0, x1,
+                       ld, n, norm, floor_, Tg);
+    return hipGetLastError();
+}
+
+}  // namespace adm1

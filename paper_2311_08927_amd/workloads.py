@@ -137,6 +137,52 @@ def batched_population(n: int = 1 << 20, seed: int = 2, steps: int = 10,
     return w
 
 
+TANK_R, TANK_H = 0.1, 0.3          # m, lab-scale cylinder (sec. 3.2 scale)
+MIXER_RPM = 12.0                    # paper Table 2
+INLET_Z, INLET_R = 0.28, 0.03       # top inlet region, m
+FLOW_MODES = 4
+
+
+def flow_field(seed: int = 3) -> dict:
+    """Seeded smooth flow: solid-body rotation at the mixer speed plus four
+    axisymmetric stream-function modes with N(0, 0.5^2) amplitudes."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 11])))
+    a = 0.5 * g.standard_normal(FLOW_MODES)
+    return {"omega": MIXER_RPM * 2 * np.pi / 60.0, "R": TANK_R, "H": TANK_H,
+            "a": [float(v) for v in a]}
+
+
+def cylinder_positions(n: int, seed: int, ld: int | None = None) -> np.ndarray:
+    """float32 [3][ld] positions uniform in the tank volume."""
+    ld = pad_ld(n) if ld is None else ld
+    P = np.zeros((3, ld), dtype=np.float32)
+    for a_, b_, g in _chunks(n, seed + 2000):
+        u = g.random((3, b_ - a_))
+        r = TANK_R * np.sqrt(u[0])
+        th = 2 * np.pi * u[1]
+        P[0, a_:b_] = r * np.cos(th)
+        P[1, a_:b_] = r * np.sin(th)
+        P[2, a_:b_] = TANK_H * u[2]
+    return P
+
+
+def digester_field(n: int = 1 << 22, seed: int = 3, steps: int = 96,
+                   T_K: float = 308.5) -> Workload:
+    """Lab-digester field: particles uniform in the cylinder (r 0.1 m,
+    h 0.3 m) advected by the seeded flow between coupling steps; particles
+    in the top inlet (z >= 0.28 m, r <= 0.03 m) at the start of an interval
+    receive the pulse feed at D = 1 1/d, the others are closed; T = 308.5 K
+    (paper Table 2).  Liquid volume per particle = tank volume / n."""
+    X = perturbed_states(n, seed)
+    pos = cylinder_positions(n, seed, X.shape[1])
+    feed = np.stack([nominal()["feed"], pulse_feed()])
+    w = Workload("digester", n, X.shape[1], X, np.full(n, T_K), np.zeros(n),
+                 np.zeros(n, dtype=np.int32), feed, steps=steps)
+    w.extra = {"pos": pos, "flow": flow_field(seed),
+               "V_p": np.pi * TANK_R ** 2 * TANK_H / n}
+    return w
+
+
 def subset(w: Workload, idx: np.ndarray) -> Workload:
     """The particles idx of w as their own workload (for oracle samples)."""
     idx = np.asarray(idx)

@@ -1,0 +1,118 @@
+"""GPU tests of the runtime pieces: HIP-graph capture of a coupling step,
+the autotuner and the launch-configuration setter (through the C ABI)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle.adm1 import Oracle
+from paper_2311_08927_amd import workloads as W
+from tests.gpu_common import PARITY_TOL, DeviceWorkload, parity
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make_ctx(n_max, **kw):
+    from paper_2311_08927_amd.adm1 import Context
+    return Context(n_max, rtol=RTOL, atol=W.atol_vector(RTOL), **kw)
+
+
+def test_graph_replay_matches_eager(torch_cuda):
+    """Replays of a captured coupling step equal the eager steps bit for bit,
+    with unrelated GPU work and host synchronisations between replays; a
+    feed change between replays is picked up."""
+    torch = torch_cuda
+    from paper_2311_08927_amd import adm1 as A
+    w = W.batched_population(4096, seed=7)
+    ctx = make_ctx(w.ld, variant=A.VARIANT_SPARSE2)
+    eager = DeviceWorkload(w)
+    graphd = DeviceWorkload(w)
+    V = torch.full((w.n,), 1.0, dtype=torch.float64, device="cuda")
+    outs = {}
+    for tag, dw in (("e", eager), ("g", graphd)):
+        outs[tag] = dict(q=torch.empty(w.n, dtype=torch.float64, device="cuda"),
+                         qc=torch.empty(w.n, dtype=torch.float64, device="cuda"),
+                         tot=torch.empty(4, dtype=torch.float64, device="cuda"))
+    s = torch.cuda.Stream()
+    feed_g = A.feed_struct(graphd.D, graphd.fidx, graphd.S_in)
+    aux_g = A.adm1_aux(graphd.H.data_ptr(), graphd.hlast.data_ptr())
+    og = outs["g"]
+    g = A.adm1_graph_capture_step(ctx.handle, graphd.X, w.ld, graphd.T, feed_g, w.dt, w.n,
+                                  aux_g, graphd.status, graphd.nsteps, V, og["q"], og["qc"],
+                                  og["tot"], s)
+    try:
+        junk = torch.zeros(1 << 20, device="cuda")
+        for k in range(4):
+            D = torch.from_numpy(w.D_at(k)).cuda()
+            eager.D.copy_(D)
+            graphd.D.copy_(D)
+            torch.cuda.synchronize()
+            ctx.step(eager.X, eager.T, eager.D, eager.fidx, eager.S_in, w.dt, n=w.n,
+                     H=eager.H, hlast=eager.hlast, status=eager.status, nsteps=eager.nsteps)
+            oe = outs["e"]
+            A.adm1_gas_flux(ctx.handle, eager.X, w.ld, eager.T, V, w.n, oe["q"], oe["qc"],
+                            oe["tot"])
+            torch.cuda.synchronize()
+            junk.add_(1.0)  # unrelated eager work between replays
+            A.adm1_graph_launch(g, s)
+            s.synchronize()
+            assert torch.equal(eager.X, graphd.X), k
+            assert torch.equal(oe["tot"], og["tot"]), k
+            assert torch.equal(eager.nsteps, graphd.nsteps), k
+    finally:
+        A.adm1_graph_destroy(g)
+
+
+def test_autotune_and_launch_setting(torch_cuda, tmp_path, monkeypatch):
+    torch = torch_cuda
+    from paper_2311_08927_amd import adm1 as A
+    from paper_2311_08927_amd import autotune as AT
+    monkeypatch.setattr(AT, "CACHE", str(tmp_path / "tune.json"))
+    w = W.batched_population(8192, seed=8)
+    ctx = make_ctx(w.ld)
+    dw = DeviceWorkload(w)
+    res = AT.autotune(ctx, dw.X, dw.T, dw.D, dw.fidx, dw.S_in, w.dt, n=w.n, tag="test")
+    assert tuple(res["choice"]) in [tuple(c) for c in AT.CANDIDATES]
+    assert len(res["timings_ms"]) == len(AT.CANDIDATES)
+    print("autotune:", res)
+    # cached second call
+    res2 = AT.autotune(ctx, dw.X, dw.T, dw.D, dw.fidx, dw.S_in, w.dt, n=w.n, tag="test")
+    assert res2["choice"] == res["choice"]
+    # the tuned launch gives the oracle's answer on a slice
+    sub = W.subset(w, np.arange(0, w.n, 97))
+    dsub = DeviceWorkload(sub)
+    ctx.step(dsub.X, dsub.T, dsub.D, dsub.fidx, dsub.S_in, sub.dt, n=sub.n)
+    orc = Oracle(W.params_path(), rtol=RTOL, atol=W.atol_vector(RTOL))
+    Xo = sub.X.copy()
+    orc.step(Xo, sub.T, sub.D, sub.fidx, sub.feed, sub.dt, n=sub.n)
+    assert parity(dsub.X.cpu().numpy(), Xo, sub.n) <= PARITY_TOL
+    with pytest.raises(A.ADM1Error):
+        A.adm1_set_launch(ctx.handle, 7, 0)
+    with pytest.raises(A.ADM1Error):
+        A.adm1_set_launch(ctx.handle, A.VARIANT_SPARSE2, 9)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("blocks", [1, 3])
+def test_sparse2_grid_sizes(torch_cuda, blocks):
+    """The persistent kernel gives the same particles the same results
+    whatever the grid size (work-queue order does not matter)."""
+    from paper_2311_08927_amd import adm1 as A
+    w = W.cstr_population(256, seed=9)
+    ref = make_ctx(w.ld, variant=A.VARIANT_SPARSE2)
+    d0 = DeviceWorkload(w)
+    ref.step(d0.X, d0.T, d0.D, d0.fidx, d0.S_in, w.dt, n=w.n)
+    ctx = make_ctx(w.ld)
+    A.adm1_set_launch(ctx.handle, A.VARIANT_SPARSE2, blocks)
+    d1 = DeviceWorkload(w)
+    ctx.step(d1.X, d1.T, d1.D, d1.fidx, d1.S_in, w.dt, n=w.n)
+    assert np.array_equal(d0.X.cpu().numpy(), d1.X.cpu().numpy())
