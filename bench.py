@@ -66,7 +66,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--n", type=int, default=None,
+                    help="particles (default 2^20 for the FP64 path, 2^24 for the surrogate)")
+    ap.add_argument("--path", choices=["fp64", "surrogate"], default="fp64")
+    ap.add_argument("--train-epochs", type=int, default=8)
+    ap.add_argument("--burn-in", type=int, default=2,
+                    help="surrogate path: untimed FP64 steps before the comparison")
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--cpu-sample", type=int, default=16384,
@@ -107,6 +112,8 @@ def cpu_baseline(w, rtol, n_sample, steps):
 
 def main():
     args = parse()
+    if args.n is None:
+        args.n = (1 << 24) if args.path == "surrogate" else (1 << 20)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
               "particle step shards by index range with no exchange besides four gas "
@@ -118,6 +125,8 @@ def main():
     from paper_2311_08927_amd import adm1 as A
     from paper_2311_08927_amd import flops as F
     from paper_2311_08927_amd import workloads as W
+    if args.path == "surrogate":
+        return surrogate_main(args)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -231,6 +240,156 @@ def main():
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.rtol, args.cpu_sample, args.cpu_steps)
         out["detail"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out))
+
+
+def surrogate_main(args):
+    """Gated surrogate against the FP64 path on the digester field: train the
+    network on integrator transitions of the batched population (2^20
+    particles x 16 coupling steps, particle split 90/5/5 with seed 4), then
+    run the same coupling steps (feed mask, step, gas flux, advection) of the
+    field through both paths from the same burned-in states."""
+    import torch
+
+    from paper_2311_08927_amd import adm1 as A
+    from paper_2311_08927_amd import flops as F
+    from paper_2311_08927_amd import surrogate as S
+    from paper_2311_08927_amd import workloads as W
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    wd = W.digester_field(args.n, seed=3, steps=args.burn_in + args.steps)
+    n_train = 1 << 20
+    ld_max = max(wd.ld, W.pad_ld(n_train, 64))
+    ctx = A.Context(ld_max, rtol=args.rtol, atol=W.atol_vector(args.rtol), variant=args.variant)
+    sur = S.Surrogate(ctx, ld_max, 8192)
+    floor = S.default_floor()
+    # --- training data and training (untimed) --------------------------------
+    t0 = time.perf_counter()
+    wt = W.batched_population(n_train, seed=2, steps=16)
+    sur.set_weights(S.init_params(4), S.identity_norm(floor))
+    states, Ds, ok, T = S.integrate_states(ctx, wt, 16)
+    g = np.random.default_rng(4)
+    perm = g.permutation(wt.n)
+    tr = torch.from_numpy(np.sort(perm[: int(0.9 * wt.n)])).to(dev)
+    va = torch.from_numpy(np.sort(perm[int(0.9 * wt.n): int(0.95 * wt.n)])).to(dev)
+    norm = S.fit_norm(sur, states, Ds, T, wt.dt, wt.n, floor, rows=tr)
+    sur.set_weights(S.init_params(4), norm)
+    X, Tg = S.dataset(sur, states, Ds, T, wt.dt, wt.n, rows=tr)
+    keep = ok[:, tr].reshape(-1)
+    X, Tg = X[keep].contiguous(), Tg[keep].contiguous()
+    Xv, Tv = S.dataset(sur, states, Ds, T, wt.dt, wt.n, rows=va)
+    del states
+    gen_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = S.train(sur, X, Tg, epochs=args.train_epochs, batch=8192, lr=1e-3, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    n_train_steps = args.train_epochs * (X.shape[0] // 8192)
+    val_mse = float(((sur.forward(Xv)[:, :35] - Tv) ** 2).mean())
+    del X, Tg, Xv, Tv
+    torch.cuda.empty_cache()
+    log(f"training: {gen_s:.1f} s data, {train_s:.1f} s for {n_train_steps} steps, "
+        f"val MSE {val_mse:.3e}")
+    # --- field: burn-in with the FP64 path (untimed) -----------------------
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    X = t(wd.X)
+    T = t(wd.T)
+    S_in = t(wd.feed)
+    pos = t(wd.extra["pos"])
+    flow = A.make_flow(wd.extra["flow"])
+    D = torch.zeros(wd.n, dtype=torch.float64, device=dev)
+    fidx = torch.zeros(wd.n, dtype=torch.int32, device=dev)
+    V = torch.full((wd.n,), wd.extra["V_p"], dtype=torch.float64, device=dev)
+    H = torch.full((wd.n,), -1.0, dtype=torch.float64, device=dev)
+    hl = torch.full((wd.n,), -1.0, dtype=torch.float64, device=dev)
+    status = torch.zeros(wd.n, dtype=torch.uint8, device=dev)
+    dt_s = wd.dt * 86400.0
+
+    def mask():
+        A.adm1_feed_mask(pos, wd.ld, wd.n, W.INLET_Z, W.INLET_R, 1.0, 1, 0, D, fidx)
+
+    for k in range(args.burn_in):
+        mask()
+        ctx.step(X, T, D, fidx, S_in, wd.dt, n=wd.n, H=H, hlast=hl, status=status)
+        A.adm1_advect(pos, wd.ld, wd.n, flow, dt_s, int(dt_s))
+    torch.cuda.synchronize()
+    X0, H0, hl0, pos0 = X.clone(), H.clone(), hl.clone(), pos.clone()
+    gate = S.adm1_gate(5.0, 3e-2, 3e-3)
+    K = args.steps
+    tot = {p: torch.zeros((K, 4), dtype=torch.float64, device=dev) for p in ("fp64", "sur")}
+    fb = torch.zeros(K, dtype=torch.int32, device=dev)
+    out_state, out_H, ms = {}, {}, {}
+    for path in ("fp64", "sur"):
+        X.copy_(X0); H.copy_(H0); hl.copy_(hl0); pos.copy_(pos0)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k in range(K):
+            mask()
+            if path == "fp64":
+                ctx.step(X, T, D, fidx, S_in, wd.dt, n=wd.n, H=H, hlast=hl, status=status)
+            else:
+                sur.step(X, T, D, fidx, S_in, wd.dt, gate, n=wd.n, H=H, hlast=hl,
+                         status=status, fb_count=fb[k:k + 1])
+            A.adm1_gas_flux(ctx.handle, X, wd.ld, T, V, wd.n, None, None, tot[path][k])
+            A.adm1_advect(pos, wd.ld, wd.n, flow, dt_s, int(dt_s))
+            log(f"# {path} step {k} enqueued")
+        b.record()
+        b.synchronize()
+        ms[path] = a.elapsed_time(b)
+        out_state[path], out_H[path] = X.clone(), H.clone()
+    # forward kernel alone on the field's features (MFMA roofline)
+    Xf = sur.featurize(X0, T, D, wd.dt, wd.n)
+    sur.forward(Xf)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sur.forward(Xf)
+    e1.record()
+    e1.synchronize()
+    fwd_ms = e0.elapsed_time(e1)
+    mlp_flop = 2.0 * (38 * 256 + 3 * 256 * 256 + 256 * 35) * wd.n
+    ch4 = tot["fp64"][:, 2].cpu().numpy(), tot["sur"][:, 2].cpu().numpy()
+    ch4_err = (np.abs(ch4[1] - ch4[0]) / np.abs(ch4[0])).tolist()
+    ph_f = -torch.log10(out_H["fp64"])
+    ph_s = -torch.log10(out_H["sur"])
+    eph = ((ph_s - ph_f).abs() / ph_f).float()
+    value = wd.n * K / (ms["sur"] / 1e3)
+    v64 = wd.n * K / (ms["fp64"] / 1e3)
+    out = {
+        "metric": "ADM1 particle-steps/sec (FP64 integrator vs gated surrogate) at stated error",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": args.burn_in,
+        "ms_per_step": ms["sur"] / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+f64", "data": "synthetic",
+        "config": {"workload": f"digester field: {wd.n} particles in the r 0.1 m, h 0.3 m "
+                               f"cylinder, seeded flow, top-inlet pulse feed, 308.5 K, "
+                               f"{K} coupling steps of 1/96 d after {args.burn_in} FP64 "
+                               f"burn-in steps", "path": "gated surrogate",
+                   "gate": {"max_dlog": gate.max_dlog, "tol_ion": gate.tol_ion,
+                            "tol_closure": gate.tol_closure}},
+        "roofline": {"bound": "mfma", "achieved": mlp_flop / (fwd_ms / 1e3) / 1e12,
+                     "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": mlp_flop / (fwd_ms / 1e3) / 2.5e15, "traffic": None,
+                     "kernel": "k_mlp_fwd (BF16 MFMA forward)", "avg_launch_ms": fwd_ms,
+                     "flops_per_launch": mlp_flop},
+        "detail": {"fp64_particle_steps_per_s": v64, "speedup_vs_fp64": value / v64,
+                   "fallback_fraction": (fb.cpu().numpy() / wd.n).tolist(),
+                   "tank_methane_rel_err": ch4_err,
+                   "ph_rel_err_max": float(eph.max()),
+                   "ph_rel_err_p99": float(torch.quantile(eph[::max(1, wd.n >> 22)], 0.99)),
+                   "train": {"transitions": int(keep.sum()), "epochs": args.train_epochs,
+                             "steps": n_train_steps, "seconds": train_s,
+                             "data_seconds": gen_s, "loss_first_last": [hist[0], hist[-1]],
+                             "val_mse": val_mse,
+                             "train_flop_per_s": 3 * mlp_flop / wd.n * 8192 *
+                             n_train_steps / train_s}},
+    }
     print(json.dumps(out))
 
 

@@ -251,6 +251,125 @@ int adm1_feed_mask(const float *pos, int64_t ld, int64_t n, double z_min, double
                    double D_zone, int32_t fidx_zone, int32_t fidx_out, double *D,
                    int32_t *fidx, uint8_t *flag, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the particle step.  The paper (sec. 2.2) keeps the
+ * stiff acid-base and hydrogen dynamics algebraic (eqs. 7-8) because they
+ * cripple explicit integration; here an MLP proposes the whole state after
+ * one interval, an FP64 gate built on those same balances accepts or rejects
+ * each proposal, and rejected particles are integrated exactly.
+ *
+ * Network 38 -> 256 -> 256 -> 256 -> 256 -> 35, GELU (erf form) after the
+ * four hidden layers.  Input features (FP32, standardised, rounded to BF16,
+ * row of 64 with columns 38..63 zero): log(max(x_k, floor_k)) for the 35
+ * state entries, T (K), log(dt) and the feed flag (1 when D > 0).  Output:
+ * the standardised increments of log(max(x_k, floor_k)) over the interval
+ * (FP32, row of 48, columns 35..47 unused).  Weights BF16, accumulation and
+ * outputs FP32; training keeps FP32 master weights and Adam moments
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error.
+ *
+ * Parameter vectors exchanged with the host (float32, ADM1_MLP_PARAMS
+ * entries) hold, layer by layer, W ([in][out], row-major) then b ([out]).
+ * ------------------------------------------------------------------------ */
+#define ADM1_MLP_IN 38
+#define ADM1_MLP_HIDDEN 256
+#define ADM1_MLP_OUT 35
+#define ADM1_MLP_PARAMS 216355
+#define ADM1_MLP_FEAT_LD 64  /* BF16 elements per feature row */
+#define ADM1_MLP_OUT_LD 48   /* FP32 elements per output row */
+
+typedef struct adm1_mlp_norm {
+    float in_mean[ADM1_MLP_IN], in_sd[ADM1_MLP_IN];
+    float out_mean[ADM1_MLP_OUT], out_sd[ADM1_MLP_OUT];
+    double floor[ADM1_MLP_OUT]; /* floor_k > 0, per state entry */
+} adm1_mlp_norm;
+
+/* Acceptance thresholds of a proposal x^ = max(x, floor) exp(delta); every
+ * test is strict, so an all-zero gate sends every particle to the exact
+ * integrator.
+ *   max_dlog:    |delta_k| for every entry;
+ *   tol_ion:     proposed ions and S_h2 against their eq. 7 / eq. 8 values at
+ *                the proposal's totals, relative to max(|value|, 100 floor);
+ *   tol_closure: COD (liquid and headspace) and nitrogen balances over the
+ *                interval (eq. 2 summed with COD and N weights): the change
+ *                of each total must lie within dt times the range its
+ *                boundary flux (dilution exchange, gas outflow) can span
+ *                when each factor of the flux moves monotonically between
+ *                its end-point values; the distance outside, relative to
+ *                the pre-step total, is compared. */
+typedef struct adm1_gate {
+    double max_dlog;
+    double tol_ion;
+    double tol_closure;
+} adm1_gate;
+
+typedef struct adm1_surrogate adm1_surrogate;
+
+/* Surrogate on a context: buffers for inference over up to n_max particles
+ * (n_max <= the context's) and training batches of up to batch_max rows.
+ * Weights start at zero.  Synchronous. */
+int adm1_surrogate_create(adm1_ctx *ctx, int64_t n_max, int64_t batch_max,
+                          adm1_surrogate **out);
+
+/* Load weights (host float32 [ADM1_MLP_PARAMS]) and normalisation (host
+ * struct); resets the Adam moments.  Synchronous. */
+int adm1_surrogate_set_weights(adm1_surrogate *s, const float *params,
+                               const adm1_mlp_norm *norm);
+
+/* Copy the FP32 master weights (nullable) and normalisation (nullable) to
+ * the host.  Synchronous. */
+int adm1_surrogate_get_weights(adm1_surrogate *s, float *params, adm1_mlp_norm *norm);
+
+/* Copy the gradients of the last training step (host float32
+ * [ADM1_MLP_PARAMS], same layout as the weights).  Synchronous. */
+int adm1_surrogate_get_grads(adm1_surrogate *s, float *grads);
+
+/* Network inputs of particles 0..n-1: X = BF16 [n][64] (uint16 bit patterns).
+ * D: [n] dilution rates (the feed flag is D > 0). */
+int adm1_surrogate_featurize(adm1_surrogate *s, const double *state, int64_t ld,
+                             const double *temp_K, const double *D, double dt_days, int64_t n,
+                             uint16_t *X, void *stream);
+
+/* Training targets from a pair of states one interval apart: float32
+ * [n][35] standardised increments of log(max(x, floor)). */
+int adm1_surrogate_targets(adm1_surrogate *s, const double *x0, const double *x1, int64_t ld,
+                           int64_t n, float *target, void *stream);
+
+/* Network outputs Y = float32 [n][48] for inputs X = BF16 [n][64]. */
+int adm1_surrogate_forward(adm1_surrogate *s, const uint16_t *X, int64_t n, float *Y,
+                           void *stream);
+
+/* The gate alone, on given network outputs Y ([n][48]): accepted particles
+ * get the proposal with eq. 7 / eq. 8 values in entries 7 and 26..31,
+ * status 0, nsteps 0 and (aux->H) the solved S_H+; rejected particles keep
+ * their state and have their index appended to fb_idx ([n] int32), in no
+ * particular order; *fb_count (device int32) is set to their number.
+ * route (nullable): [n] uint8, 1 accepted / 0 rejected. */
+int adm1_surrogate_gate(adm1_surrogate *s, double *state, int64_t ld, const double *temp_K,
+                        const adm1_feed *feed, double dt_days, int64_t n, const float *Y,
+                        const adm1_gate *gate, adm1_aux *aux, uint8_t *status,
+                        int32_t *nsteps, uint8_t *route, int32_t *fb_idx, int32_t *fb_count,
+                        void *stream);
+
+/* One coupling step through the surrogate: featurize, forward, gate, then
+ * the exact step (ADM1_VARIANT_SPARSE2 kernel) on the rejected particles
+ * from their pre-step states.  Arguments as in adm1_step_particles and
+ * adm1_surrogate_gate; fb_count (nullable, device int32) receives the number
+ * of rejected particles.  n <= the surrogate's n_max. */
+int adm1_surrogate_step(adm1_surrogate *s, double *state, int64_t ld, const double *temp_K,
+                        const adm1_feed *feed, double dt_days, int64_t n,
+                        const adm1_gate *gate, adm1_aux *aux, uint8_t *status,
+                        int32_t *nsteps, uint8_t *route, int32_t *fb_count, void *stream);
+
+/* One training step on a batch of B rows: X BF16 [B][64], target float32
+ * [B][35]; forward, mean-squared-error loss (written to *loss, device
+ * float32, before the update), backward, Adam with learning rate lr at step
+ * number `step` (>= 1, for the bias corrections). */
+int adm1_surrogate_train_step(adm1_surrogate *s, const uint16_t *X, const float *target,
+                              int64_t B, float lr, int32_t step, float *loss, void *stream);
+
+/* Free the surrogate.  Synchronous.  NULL is a no-op. */
+void adm1_surrogate_destroy(adm1_surrogate *s);
+
 /* Comma-separated adm1_params field names in struct order (static string). */
 const char *adm1_param_names(void);
 

@@ -8,23 +8,10 @@
 #include <new>
 
 #include "adm1.h"
+#include "adm1_ctx.h"
 #include "adm1_kernels.h"
 
 using adm1::DevParams;
-
-struct adm1_ctx {
-    DevParams dp;
-    adm1_opts opts;
-    int64_t n_max;
-    int device;
-    int32_t* d_queue;    // work-queue counter
-    double* d_partial;   // gas-flux block partials [kGasBlocks][4]
-    double* d_work;      // stage vectors of the two-lane step kernel
-    DevParams* d_params; // device copy of dp
-    int64_t work_blocks;
-    int tuned_variant;   // autotuned step variant (-1: not tuned)
-    int tuned_blocks_per_cu;
-};
 
 namespace {
 
@@ -207,6 +194,10 @@ int apply_opts(const adm1_opts& o, DevParams& d)
     return ADM1_OK;
 }
 
+}  // namespace
+
+namespace adm1_abi {
+
 bool is_device(const void* ptr)
 {
     if (!ptr) return false;
@@ -238,7 +229,9 @@ int check_feed(const adm1_feed* feed)
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? ADM1_OK : (int)e; }
 
-}  // namespace
+}  // namespace adm1_abi
+
+using namespace adm1_abi;
 
 extern "C" {
 
@@ -274,6 +267,7 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
     if (rc == ADM1_OK) rc = apply_opts(*o, c->dp);
     if (rc != ADM1_OK) { delete c; return rc; }
     c->opts = *o;
+    c->raw = *p;
     c->n_max = n_max;
     c->tuned_variant = -1;
     c->tuned_blocks_per_cu = 0;

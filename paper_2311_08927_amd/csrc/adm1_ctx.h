@@ -1,0 +1,30 @@
+// The library context behind the opaque adm1_ctx handle, and the argument
+// checks shared by the entry points (internal header).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adm1.h"
+#include "adm1_devparams.h"
+
+struct adm1_ctx {
+    adm1::DevParams dp;
+    adm1_params raw;     // parameters as given (the surrogate gate derives from them)
+    adm1_opts opts;
+    int64_t n_max;
+    int device;
+    int32_t* d_queue;    // work-queue counter
+    double* d_partial;   // gas-flux block partials [kGasBlocks][4]
+    double* d_work;      // stage vectors of the two-lane step kernel
+    adm1::DevParams* d_params;  // device copy of dp
+    int64_t work_blocks;
+    int tuned_variant;   // step variant chosen by adm1_set_launch (-1: none)
+    int tuned_blocks_per_cu;
+};
+
+namespace adm1_abi {
+bool is_device(const void* ptr);
+int check_layout(const adm1_ctx* ctx, int64_t ld, int64_t n);
+int check_feed(const adm1_feed* feed);
+int hip_rc(hipError_t e);
+}  // namespace adm1_abi

@@ -192,12 +192,16 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = kb; k0 < ke; k0 += 16) {
+        // consecutive threads walk the unit-stride index of each operand
         for (int e = threadIdx.x; e < 64 * 16; e += kThreads) {
-            const int r = e >> 4, kk = e & 15;
-            const int k = k0 + kk;
-            const int m = m0 + r, nn = n0 + r;
-            As[r][kk] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0;
-            Bs[r][kk] = (nn < g.N && k < ke) ? g.B[(int64_t)k * g.sbk + (int64_t)nn * g.sbn] : 0;
+            const int ra = g.sak == 1 ? e >> 4 : e & 63, ka = g.sak == 1 ? e & 15 : e >> 6;
+            const int rb = g.sbk == 1 ? e >> 4 : e & 63, kb2 = g.sbk == 1 ? e & 15 : e >> 6;
+            const int m = m0 + ra, nn = n0 + rb;
+            const int kA = k0 + ka, kB = k0 + kb2;
+            As[ra][ka] =
+                (m < g.M && kA < ke) ? g.A[(int64_t)m * g.sam + (int64_t)kA * g.sak] : 0;
+            Bs[rb][kb2] =
+                (nn < g.N && kB < ke) ? g.B[(int64_t)kB * g.sbk + (int64_t)nn * g.sbn] : 0;
         }
         __syncthreads();
         s16x4 af;

@@ -1,0 +1,328 @@
+"""ctypes binding of the learned-surrogate entry points of libadm1.so and the
+host-side training driver.
+
+Argument marshalling only: featurisation, the network, its loss, backward
+pass and optimiser, the gate and the fallback integration all run in the
+HIP kernels.  The training driver here only orchestrates: it runs the FP64
+integrator to produce transitions, asks the kernels for raw features and
+targets to take their mean and spread, shuffles batch indices and calls the
+training step.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from . import adm1 as A
+from . import workloads as W
+
+IN, HID, OUT = 38, 256, 35
+NPARAMS = 216355
+FEAT_LD, OUT_LD = 64, 48
+
+_ready = False
+
+
+class adm1_mlp_norm(ctypes.Structure):
+    _fields_ = [("in_mean", ctypes.c_float * IN), ("in_sd", ctypes.c_float * IN),
+                ("out_mean", ctypes.c_float * OUT), ("out_sd", ctypes.c_float * OUT),
+                ("floor", ctypes.c_double * OUT)]
+
+
+class adm1_gate(ctypes.Structure):
+    _fields_ = [("max_dlog", ctypes.c_double), ("tol_ion", ctypes.c_double),
+                ("tol_closure", ctypes.c_double)]
+
+
+def _lib():
+    global _ready
+    L = A.lib()
+    if not _ready:
+        vp, i64, i32, dbl, flt = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                  ctypes.c_double, ctypes.c_float)
+        sig = {
+            "adm1_surrogate_create": [vp, i64, i64, ctypes.POINTER(vp)],
+            "adm1_surrogate_set_weights": [vp, vp, vp],
+            "adm1_surrogate_get_weights": [vp, vp, vp],
+            "adm1_surrogate_get_grads": [vp, vp],
+            "adm1_surrogate_featurize": [vp, vp, i64, vp, vp, dbl, i64, vp, vp],
+            "adm1_surrogate_targets": [vp, vp, vp, i64, i64, vp, vp],
+            "adm1_surrogate_forward": [vp, vp, i64, vp, vp],
+            "adm1_surrogate_gate": [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, vp,
+                                    vp, vp],
+            "adm1_surrogate_step": [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, vp],
+            "adm1_surrogate_train_step": [vp, vp, vp, i64, flt, i32, vp, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.restype = ctypes.c_int
+            f.argtypes = args
+        L.adm1_surrogate_destroy.argtypes = [vp]
+        L.adm1_surrogate_destroy.restype = None
+        _ready = True
+    return L
+
+
+_p, _s, _check = A._ptr, A._stream, A._check
+
+
+def make_norm(in_mean, in_sd, out_mean, out_sd, floor) -> adm1_mlp_norm:
+    f = lambda a, n: (ctypes.c_float * n)(*np.asarray(a, np.float32).tolist())  # noqa: E731
+    return adm1_mlp_norm(f(in_mean, IN), f(in_sd, IN), f(out_mean, OUT), f(out_sd, OUT),
+                         (ctypes.c_double * OUT)(*np.asarray(floor, np.float64).tolist()))
+
+
+def norm_dict(n: adm1_mlp_norm) -> dict:
+    return {k: np.array(getattr(n, k)) for k in ("in_mean", "in_sd", "out_mean", "out_sd",
+                                                 "floor")}
+
+
+def identity_norm(floor) -> adm1_mlp_norm:
+    return make_norm(np.zeros(IN), np.ones(IN), np.zeros(OUT), np.ones(OUT), floor)
+
+
+def init_params(seed: int) -> np.ndarray:
+    """Initial weights: W ~ N(0, 1/fan_in) per layer, zero biases (seeded);
+    flat float32 vector in the ABI's layer order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, o in ((IN, HID), (HID, HID), (HID, HID), (HID, HID), (HID, OUT)):
+        parts += [(rng.standard_normal((i, o)) / math.sqrt(i)).ravel(), np.zeros(o)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def default_floor() -> np.ndarray:
+    """Per-entry floor of the log features: 1e-6 of the nominal state."""
+    return 1e-6 * W.nominal()["state"]
+
+
+# ---------------------------------------------------------------------------
+# C-named entry points
+# ---------------------------------------------------------------------------
+def adm1_surrogate_create(ctx: int, n_max: int, batch_max: int) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib().adm1_surrogate_create(ctx, int(n_max), int(batch_max), ctypes.byref(h)),
+           "adm1_surrogate_create")
+    return h.value
+
+
+def adm1_surrogate_destroy(s: int):
+    _lib().adm1_surrogate_destroy(s)
+
+
+def adm1_surrogate_set_weights(s: int, params: np.ndarray, norm: adm1_mlp_norm):
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    assert params.size == NPARAMS
+    _check(_lib().adm1_surrogate_set_weights(s, params.ctypes.data, ctypes.byref(norm)),
+           "adm1_surrogate_set_weights")
+
+
+def adm1_surrogate_get_weights(s: int):
+    params = np.empty(NPARAMS, dtype=np.float32)
+    norm = adm1_mlp_norm()
+    _check(_lib().adm1_surrogate_get_weights(s, params.ctypes.data, ctypes.byref(norm)),
+           "adm1_surrogate_get_weights")
+    return params, norm
+
+
+def adm1_surrogate_get_grads(s: int) -> np.ndarray:
+    g = np.empty(NPARAMS, dtype=np.float32)
+    _check(_lib().adm1_surrogate_get_grads(s, g.ctypes.data), "adm1_surrogate_get_grads")
+    return g
+
+
+def adm1_surrogate_featurize(s, state, ld, temp_K, D, dt_days, n, X, stream=None):
+    _check(_lib().adm1_surrogate_featurize(s, _p(state), int(ld), _p(temp_K), _p(D),
+                                           float(dt_days), int(n), _p(X), _s(stream)),
+           "adm1_surrogate_featurize")
+
+
+def adm1_surrogate_targets(s, x0, x1, ld, n, target, stream=None):
+    _check(_lib().adm1_surrogate_targets(s, _p(x0), _p(x1), int(ld), int(n), _p(target),
+                                         _s(stream)), "adm1_surrogate_targets")
+
+
+def adm1_surrogate_forward(s, X, n, Y, stream=None):
+    _check(_lib().adm1_surrogate_forward(s, _p(X), int(n), _p(Y), _s(stream)),
+           "adm1_surrogate_forward")
+
+
+def adm1_surrogate_gate(s, state, ld, temp_K, feed, dt_days, n, Y, gate: adm1_gate, aux,
+                        status, nsteps, route, fb_idx, fb_count, stream=None):
+    _check(_lib().adm1_surrogate_gate(
+        s, _p(state), int(ld), _p(temp_K), ctypes.byref(feed), float(dt_days), int(n), _p(Y),
+        ctypes.byref(gate), None if aux is None else ctypes.byref(aux), _p(status),
+        _p(nsteps), _p(route), _p(fb_idx), _p(fb_count), _s(stream)), "adm1_surrogate_gate")
+
+
+def adm1_surrogate_step(s, state, ld, temp_K, feed, dt_days, n, gate: adm1_gate, aux, status,
+                        nsteps=None, route=None, fb_count=None, stream=None):
+    _check(_lib().adm1_surrogate_step(
+        s, _p(state), int(ld), _p(temp_K), ctypes.byref(feed), float(dt_days), int(n),
+        ctypes.byref(gate), None if aux is None else ctypes.byref(aux), _p(status),
+        _p(nsteps), _p(route), _p(fb_count), _s(stream)), "adm1_surrogate_step")
+
+
+def adm1_surrogate_train_step(s, X, target, B, lr, step, loss, stream=None):
+    _check(_lib().adm1_surrogate_train_step(s, _p(X), _p(target), int(B), float(lr), int(step),
+                                            _p(loss), _s(stream)),
+           "adm1_surrogate_train_step")
+
+
+# ---------------------------------------------------------------------------
+# Wrapper and training driver
+# ---------------------------------------------------------------------------
+class Surrogate:
+    """A surrogate bound to a Context (paper_2311_08927_amd.adm1.Context)."""
+
+    def __init__(self, ctx, n_max: int, batch_max: int = 8192):
+        self.ctx = ctx
+        self.handle = adm1_surrogate_create(ctx.handle, n_max, batch_max)
+        self.n_max, self.batch_max = n_max, batch_max
+        self.norm = None
+
+    def close(self):
+        if self.handle:
+            adm1_surrogate_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, params, norm: adm1_mlp_norm):
+        adm1_surrogate_set_weights(self.handle, params, norm)
+        self.norm = norm
+
+    def get_weights(self):
+        return adm1_surrogate_get_weights(self.handle)
+
+    def featurize(self, state, T, D, dt, n=None):
+        import torch
+        n = state.shape[1] if n is None else n
+        X = torch.empty((max(n, 1), FEAT_LD), dtype=torch.int16, device=state.device)
+        adm1_surrogate_featurize(self.handle, state, state.shape[1], T, D, dt, n, X)
+        return X[:n]
+
+    def targets(self, x0, x1, n=None):
+        import torch
+        n = x0.shape[1] if n is None else n
+        Tg = torch.empty((max(n, 1), OUT), dtype=torch.float32, device=x0.device)
+        adm1_surrogate_targets(self.handle, x0, x1, x0.shape[1], n, Tg)
+        return Tg[:n]
+
+    def forward(self, X):
+        import torch
+        n = X.shape[0]
+        Y = torch.empty((max(n, 1), OUT_LD), dtype=torch.float32, device=X.device)
+        adm1_surrogate_forward(self.handle, X, n, Y)
+        return Y[:n]
+
+    def step(self, state, T, D, fidx, S_in, dt, gate: adm1_gate, n=None, H=None, hlast=None,
+             status=None, nsteps=None, route=None, fb_count=None, stream=None):
+        import torch
+        n = state.shape[1] if n is None else n
+        if status is None:
+            status = torch.empty(max(n, 1), dtype=torch.uint8, device=state.device)
+        aux = None if H is None and hlast is None else A.adm1_aux(_p(H), _p(hlast))
+        adm1_surrogate_step(self.handle, state, state.shape[1], T, A.feed_struct(D, fidx, S_in),
+                            dt, n, gate, aux, status, nsteps, route, fb_count, stream)
+        return status
+
+    def train_step(self, X, target, lr, step, loss):
+        adm1_surrogate_train_step(self.handle, X, target, X.shape[0], lr, step, loss)
+
+
+def integrate_states(ctx, w: W.Workload, steps: int):
+    """Advance w with the FP64 integrator for `steps` coupling intervals.
+    Returns the device states X_0..X_steps ([35][ld] each), the dilution
+    rates of each interval and a mask [steps][n] of clean steps (status 0)."""
+    import torch
+    dev = "cuda"
+    X = torch.from_numpy(np.ascontiguousarray(w.X)).to(dev)
+    T = torch.from_numpy(w.T).to(dev)
+    fidx = torch.from_numpy(w.fidx).to(dev)
+    S_in = torch.from_numpy(w.feed).to(dev)
+    H = torch.full((w.n,), -1.0, dtype=torch.float64, device=dev)
+    hl = torch.full((w.n,), -1.0, dtype=torch.float64, device=dev)
+    status = torch.empty(w.n, dtype=torch.uint8, device=dev)
+    states, Ds, ok = [X.clone()], [], []
+    for s in range(steps):
+        D = torch.from_numpy(w.D_at(s)).to(dev)
+        ctx.step(X, T, D, fidx, S_in, w.dt, n=w.n, H=H, hlast=hl, status=status)
+        states.append(X.clone())
+        Ds.append(D)
+        ok.append(status == 0)
+    return states, Ds, torch.stack(ok), T
+
+
+def dataset(sur: "Surrogate", states, Ds, T, dt, n, rows=None):
+    """Features and targets (kernel outputs under the surrogate's current
+    normalisation) of every transition, stacked step by step; `rows`
+    (optional index tensor) selects particles."""
+    import torch
+    feats, targs = [], []
+    for s in range(len(Ds)):
+        x0, x1 = states[s], states[s + 1]
+        Xs = sur.featurize(x0, T, Ds[s], dt, n)
+        Ts = sur.targets(x0, x1, n)
+        if rows is not None:
+            Xs, Ts = Xs.index_select(0, rows), Ts.index_select(0, rows)
+        feats.append(Xs.clone())
+        targs.append(Ts.clone())
+    return torch.cat(feats), torch.cat(targs)
+
+
+def fit_norm(sur: "Surrogate", states, Ds, T, dt, n, floor, rows=None) -> adm1_mlp_norm:
+    """Normalisation from the raw (identity-normalised) features and targets
+    of the training transitions: per-column mean and spread; columns without
+    spread keep unit scale."""
+    params, _ = sur.get_weights()
+    sur.set_weights(params, identity_norm(floor))
+    Xr, Tr = dataset(sur, states, Ds, T, dt, n, rows)
+    xf = bf16_to_float(Xr[:, :IN])
+    in_mean = xf.mean(0).double().cpu().numpy()
+    in_sd = xf.std(0).double().cpu().numpy()
+    in_sd = np.where(in_sd > 1e-6, in_sd, 1.0)
+    out_mean = Tr.mean(0).double().cpu().numpy()
+    out_sd = Tr.std(0).double().cpu().numpy()
+    out_sd = np.where(out_sd > 1e-8, out_sd, 1.0)
+    return make_norm(in_mean, in_sd, out_mean, out_sd, floor)
+
+
+def bf16_to_float(Xb):
+    """BF16 bit patterns (int16 tensor) -> float32 tensor."""
+    import torch
+    return (Xb.to(torch.int32) << 16).view(torch.float32)
+
+
+def train(sur: Surrogate, X, Tg, epochs: int, batch: int = 8192, lr: float = 1e-3,
+          seed: int = 4, log=None):
+    """Adam on (X, Tg) (device tensors, already standardised) with a cosine
+    learning-rate schedule; returns the per-epoch mean losses."""
+    import torch
+    n = X.shape[0]
+    nb = n // batch
+    total = max(1, epochs * nb)
+    loss = torch.zeros(max(nb, 1), dtype=torch.float32, device=X.device)
+    g = torch.Generator(device=X.device)
+    g.manual_seed(seed)
+    hist = []
+    k = 0
+    for e in range(epochs):
+        perm = torch.randperm(n, generator=g, device=X.device)
+        for b in range(nb):
+            idx = perm[b * batch:(b + 1) * batch]
+            xb = X.index_select(0, idx).contiguous()
+            tb = Tg.index_select(0, idx).contiguous()
+            k += 1
+            lr_k = 0.5 * lr * (1.0 + math.cos(math.pi * (k - 1) / total))
+            sur.train_step(xb, tb, lr_k, k, loss[b:b + 1])
+        hist.append(float(loss[:nb].mean()))
+        if log:
+            log(f"epoch {e}: loss {hist[-1]:.4e}")
+    return hist

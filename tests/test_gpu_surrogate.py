@@ -1,0 +1,346 @@
+"""GPU tests of the learned surrogate through the C ABI, against the FP64
+surrogate oracle (oracle/mlp.py) and the integrator oracle.
+
+Tolerances (derived from the arithmetic):
+  features / targets: the same FP32 operations on both sides; the logarithm
+    may differ by an ulp, so BF16 features agree to one BF16 ulp and FP32
+    targets to a few FP32 ulps;
+  forward: BF16 products are exact in FP32 and the 256-term FP32 sums carry
+    ~2^-24 sqrt(256) relative error, so most outputs agree to FP32 rounding
+    (median below 2^-14 of the output scale); an activation whose FP32 value
+    sits that close to a BF16 rounding boundary rounds the other way, an
+    error of one BF16 ulp (2^-8 relative) in that activation which the later
+    layers carry to the outputs: rare, but the largest differences reach a
+    few 2^-8 of the output scale (bound 2^-5, and fewer than a quarter of
+    the rows above 2^-12);
+  gradients: the backward pass rounds dZ to BF16 (2^-9 relative per entry)
+    before the products, so per-tensor relative error stays near 2^-9 and
+    cosine similarity above 0.999.
+"""
+from __future__ import annotations
+
+import json
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from oracle.adm1 import Oracle
+from paper_2311_08927_amd import workloads as W
+from tests.gpu_common import DeviceWorkload, parity
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make(n_max, batch_max=4096):
+    from paper_2311_08927_amd.adm1 import Context
+    from paper_2311_08927_amd.surrogate import Surrogate
+    ctx = Context(n_max, rtol=RTOL, atol=W.atol_vector(RTOL))
+    return ctx, Surrogate(ctx, n_max, batch_max)
+
+
+def seeded_norm(seed):
+    from paper_2311_08927_amd import surrogate as S
+    rng = np.random.default_rng(seed)
+    nom = W.nominal()["state"]
+    in_mean = np.concatenate([np.log(nom), [308.0, np.log(1 / 96), 0.05]]) + \
+        0.1 * rng.standard_normal(38)
+    in_sd = 0.5 + rng.random(38)
+    out_mean = 0.01 * rng.standard_normal(35)
+    out_sd = 0.01 + 0.1 * rng.random(35)
+    return S.make_norm(in_mean, in_sd, out_mean, out_sd, S.default_floor())
+
+
+def seeded_params(seed):
+    rng = np.random.default_rng(seed)
+    p = M.init_params(seed).astype(np.float64)
+    p += 0.02 * rng.standard_normal(p.size)   # non-zero biases too
+    return p.astype(np.float32)
+
+
+def bits_to_bf16_values(t):
+    return M.bf16_value(t.cpu().numpy().view(np.uint16))
+
+
+def test_featurize_and_targets_match_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_2311_08927_amd import surrogate as S
+    w = W.cstr_population(256, seed=1)
+    orc = Oracle(W.params_path(), rtol=RTOL, atol=W.atol_vector(RTOL))
+    X1 = w.X.copy()
+    orc.step(X1, w.T, w.D, w.fidx, w.feed, w.dt, n=w.n)
+    ctx, sur = make(w.ld)
+    norm = seeded_norm(3)
+    sur.set_weights(seeded_params(1), norm)
+    nd = S.norm_dict(norm)
+    dw = DeviceWorkload(w)
+    Xg = sur.featurize(dw.X, dw.T, dw.D, w.dt, w.n)
+    ref_bits = M.bf16_bits(M.features(w.X[:, :w.n], w.T[:w.n], w.D[:w.n], w.dt, nd)
+                           .astype(np.float32))
+    got_bits = Xg.cpu().numpy().view(np.uint16)
+    assert np.all(got_bits[:, 38:] == 0)
+    diff = np.abs(got_bits[:, :38].astype(np.int32) - ref_bits.astype(np.int32))
+    print("feature BF16 ulp differences:", np.bincount(diff.ravel()))
+    assert diff.max() <= 1 and np.mean(diff == 0) > 0.999
+    x1 = torch.from_numpy(X1).cuda()
+    Tg = sur.targets(dw.X, x1, w.n).cpu().numpy().astype(np.float64)
+    Tr = M.targets(w.X[:, :w.n], X1[:, :w.n], nd)
+    err = np.abs(Tg - Tr) / np.maximum(np.abs(Tr), 1.0)
+    print("target max relative difference:", err.max())
+    assert err.max() < 4 * 2.0 ** -23
+
+
+@pytest.mark.parametrize("n", [1000, 1, 128])
+def test_forward_matches_oracle(torch_cuda, n):
+    torch = torch_cuda
+    ctx, sur = make(1024)
+    p = seeded_params(7)
+    from paper_2311_08927_amd import surrogate as S
+    sur.set_weights(p, seeded_norm(3))
+    rng = np.random.default_rng(n)
+    xin = rng.standard_normal((n, 38)).astype(np.float32)
+    bits = np.zeros((n, 64), dtype=np.uint16)
+    bits[:, :38] = M.bf16_bits(xin)
+    X = torch.from_numpy(bits.view(np.int16)).cuda()
+    Y = sur.forward(X).cpu().numpy()
+    Yr, _ = M.forward(p, M.bf16_value(bits[:, :38]))
+    scale = np.sqrt(np.mean(Yr ** 2))
+    err = np.abs(Y[:, :35] - Yr) / scale
+    print(f"n={n}: forward max err / rms = {err.max():.3e}, median {np.median(err):.3e}")
+    rows = err.max(axis=1)
+    print("row max error quantiles 0.5/0.9/0.99:", np.quantile(rows, [0.5, 0.9, 0.99]))
+    assert err.max() < 2.0 ** -5 and np.median(err) < 2.0 ** -14
+    # rows touched by a rounding flip are a minority
+    assert np.mean(rows > 2.0 ** -12) < 0.25
+
+
+def test_forward_empty(torch_cuda):
+    torch = torch_cuda
+    ctx, sur = make(64)
+    from paper_2311_08927_amd import surrogate as S
+    S.adm1_surrogate_forward(sur.handle, torch.zeros((1, 64), dtype=torch.int16,
+                                                     device="cuda"), 0,
+                             torch.zeros((1, 48), device="cuda"))
+
+
+def test_gradients_and_adam_match_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_2311_08927_amd import surrogate as S
+    B = 2048
+    ctx, sur = make(64, batch_max=B)
+    p = seeded_params(11)
+    sur.set_weights(p, seeded_norm(3))
+    rng = np.random.default_rng(5)
+    bits = np.zeros((B, 64), dtype=np.uint16)
+    bits[:, :38] = M.bf16_bits(rng.standard_normal((B, 38)).astype(np.float32))
+    tgt = rng.standard_normal((B, 35)).astype(np.float32)
+    X = torch.from_numpy(bits.view(np.int16)).cuda()
+    Tt = torch.from_numpy(tgt).cuda()
+    loss = torch.zeros(1, device="cuda")
+    sur.train_step(X, Tt, 0.0, 1, loss)          # lr 0: gradients only
+    g = S.adm1_surrogate_get_grads(sur.handle).astype(np.float64)
+    lr_, gr = M.loss_and_grad(p, M.bf16_value(bits[:, :38]), tgt.astype(np.float64))
+    assert abs(float(loss.item()) - lr_) <= 1e-3 * lr_
+    o = 0
+    for li, (i, nn) in enumerate(M.DIMS):
+        for name, cnt in (("W", i * nn), ("b", nn)):
+            a, b = g[o:o + cnt], gr[o:o + cnt]
+            o += cnt
+            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+            rel = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            print(f"layer {li} {name}: cosine {cos:.6f} rel {rel:.3e}")
+            assert cos > 0.999 and rel < 2.0 ** -6
+    # one Adam step from zero moments: p - lr g / (|g| + eps) per entry
+    sur.set_weights(p, seeded_norm(3))
+    lr = 1e-3
+    sur.train_step(X, Tt, lr, 1, loss)
+    p1, _ = sur.get_weights()
+    p1r, _, _ = M.adam_step(p.astype(np.float64), gr, np.zeros_like(gr), np.zeros_like(gr),
+                            lr, 1)
+    d = np.abs(p1.astype(np.float64) - p1r)
+    print("Adam step: fraction within 1e-3 lr:", np.mean(d <= 1e-3 * lr), "max", d.max())
+    assert np.mean(d <= 1e-3 * lr + 1e-7) > 0.99 and d.max() <= 2 * lr + 1e-6
+
+
+def _burned_in(n, steps=8):
+    """Oracle states after `steps` intervals (past the initial transient),
+    the next interval's end states and the warm starts."""
+    w = W.cstr_population(n, seed=1)
+    orc = Oracle(W.params_path(), rtol=RTOL, atol=W.atol_vector(RTOL))
+    H = np.full(w.ld, -1.0)
+    hl = np.full(w.ld, -1.0)
+    X0 = w.X.copy()
+    for _ in range(steps):
+        orc.step(X0, w.T, w.D, w.fidx, w.feed, w.dt, H=H, hlast=hl, n=w.n)
+    H0 = H.copy()
+    X1 = X0.copy()
+    orc.step(X1, w.T, w.D, w.fidx, w.feed, w.dt, H=H, hlast=hl, n=w.n)
+    return w, orc, X0, X1, H0
+
+
+def test_gate_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_2311_08927_amd import adm1 as A
+    from paper_2311_08927_amd import surrogate as S
+    w, orc, X0, X1, H0 = _burned_in(256)
+    values = json.load(open(W.params_path()))["values"]
+    floor = S.default_floor()
+    delta = (np.log(np.maximum(X1, floor[:, None])) -
+             np.log(np.maximum(X0, floor[:, None])))[:, :w.n].T
+    rng = np.random.default_rng(9)
+    noisy = rng.random(w.n) < 0.5
+    scale = np.exp(rng.uniform(np.log(1e-6), np.log(1e-2), w.n))
+    delta = delta + noisy[:, None] * scale[:, None] * rng.standard_normal(delta.shape)
+    Yf = np.zeros((w.n, 48), dtype=np.float32)
+    Yf[:, :35] = delta.astype(np.float32)
+    ctx, sur = make(w.ld)
+    sur.set_weights(seeded_params(1), S.identity_norm(floor))
+    gate = S.adm1_gate(5.0, 1e-4, 1e-6)
+    dw = DeviceWorkload(w)
+    dw.X.copy_(torch.from_numpy(X0))
+    dw.H.copy_(torch.from_numpy(H0[:w.n]))
+    Y = torch.from_numpy(Yf).cuda()
+    route = torch.empty(w.n, dtype=torch.uint8, device="cuda")
+    fb_idx = torch.full((w.n,), -1, dtype=torch.int32, device="cuda")
+    fb_cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    status = torch.full((w.n,), 77, dtype=torch.uint8, device="cuda")
+    S.adm1_surrogate_gate(sur.handle, dw.X, w.ld, dw.T, A.feed_struct(dw.D, dw.fidx, dw.S_in),
+                          w.dt, w.n, Y, gate, A.adm1_aux(dw.H.data_ptr(), None), status, None,
+                          route, fb_idx, fb_cnt)
+    torch.cuda.synchronize()
+    rg = route.cpu().numpy().astype(bool)
+    xg = dw.X.cpu().numpy()
+    nom = W.nominal()["state"]
+    acc_ref = np.zeros(w.n, dtype=bool)
+    compared = 0
+    for i in range(w.n):
+        ok, xs, Hs, res = M.gate(orc, values, X0[:, i], w.T[i], w.D[i], w.feed[w.fidx[i]], w.dt,
+                                 Yf[i, :35].astype(np.float64), floor, H0[i], gate.max_dlog,
+                                 gate.tol_ion, gate.tol_closure)
+        acc_ref[i] = ok
+        near = (abs(res[1] - gate.tol_ion) < 1e-6 * gate.tol_ion or
+                abs(res[2] - gate.tol_closure) < 1e-3 * gate.tol_closure or
+                abs(res[3] - gate.tol_closure) < 1e-3 * gate.tol_closure)
+        if near:
+            continue
+        compared += 1
+        assert rg[i] == ok, (i, res)
+        if ok:
+            e = np.max(np.abs(xg[:, i] - xs) / np.maximum(np.abs(xs), 1e-4 * nom))
+            assert e < 1e-12, (i, e)
+    print(f"gate: {rg.sum()} accepted of {w.n}; compared {compared}")
+    assert 0 < rg.sum() < w.n and compared > 0.9 * w.n
+    # rejected particles are untouched and listed once
+    rej = np.flatnonzero(~rg)
+    assert np.array_equal(xg[:, rej], X0[:, rej])
+    cnt = int(fb_cnt.item())
+    assert cnt == len(rej)
+    assert np.array_equal(np.sort(fb_idx.cpu().numpy()[:cnt]), rej)
+    st = status.cpu().numpy()
+    assert np.all(st[rg] == 0) and np.all(st[~rg] == 77)
+
+
+def test_zero_gate_is_bit_identical_to_the_integrator(torch_cuda):
+    """Threshold 0 sends every particle to the exact integrator: the result
+    equals adm1_step_particles bit for bit (state, warm starts, status,
+    step counts)."""
+    torch = torch_cuda
+    from paper_2311_08927_amd import surrogate as S
+    full = W.batched_population(1 << 13, seed=2)
+    w = W.subset(full, np.arange(0, full.n, 16))
+    ctx, sur = make(w.ld)
+    sur.set_weights(seeded_params(1), S.identity_norm(S.default_floor()))
+    a, b = DeviceWorkload(w), DeviceWorkload(w)
+    zero = S.adm1_gate(0.0, 0.0, 0.0)
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for s in range(3):
+        D = torch.from_numpy(w.D_at(s)).cuda()
+        ctx.step(a.X, a.T, D, a.fidx, a.S_in, w.dt, n=w.n, H=a.H, hlast=a.hlast,
+                 status=a.status, nsteps=a.nsteps)
+        sur.step(b.X, b.T, D, b.fidx, b.S_in, w.dt, zero, n=w.n, H=b.H, hlast=b.hlast,
+                 status=b.status, nsteps=b.nsteps, fb_count=fb)
+        torch.cuda.synchronize()
+        assert int(fb.item()) == w.n
+        for t1, t2 in ((a.X, b.X), (a.H, b.H), (a.hlast, b.hlast), (a.status, b.status),
+                       (a.nsteps, b.nsteps)):
+            assert torch.equal(t1, t2)
+
+
+def test_trained_network_beats_untrained(torch_cuda):
+    """Train on integrator transitions (own forward/backward/Adam kernels);
+    on held-out particles the trained network's error is far below the
+    untrained one's, and its gated step sends fewer particles to the exact
+    integrator while the accepted ones stay within 1e-3 of it in methane
+    flow and pH."""
+    torch = torch_cuda
+    from paper_2311_08927_amd import surrogate as S
+    n_train, steps = 1 << 15, 6
+    w = W.batched_population(n_train, seed=2, steps=steps)
+    ctx, sur = make(w.ld, batch_max=1024)
+    floor = S.default_floor()
+    sur.set_weights(M.init_params(4), S.identity_norm(floor))
+    states, Ds, ok, T = S.integrate_states(ctx, w, steps)
+    norm = S.fit_norm(sur, states, Ds, T, w.dt, w.n, floor)
+    sur.set_weights(M.init_params(4), norm)
+    X, Tg = S.dataset(sur, states, Ds, T, w.dt, w.n)
+    keep = ok.reshape(-1)
+    X, Tg = X[keep].contiguous(), Tg[keep].contiguous()
+    hist = S.train(sur, X, Tg, epochs=8, batch=1024, lr=2e-3, log=print)
+    assert hist[-1] < 0.1 * hist[0]
+    # held-out particles (another seed), one interval from a state past the
+    # initial transient
+    wv = W.batched_population(2048, seed=12, steps=steps)
+    sv, Dv, okv, Tv = S.integrate_states(ctx, wv, 4)
+    Xv, Tgv = S.dataset(sur, sv[2:], Dv[2:], Tv, wv.dt, wv.n)
+    Yt = sur.forward(Xv)[:, :35]
+    mse_trained = float(((Yt - Tgv) ** 2).mean())
+    mse_zero = float((Tgv ** 2).mean())          # untrained: zero weights predict the mean
+    print(f"held-out MSE: trained {mse_trained:.3e}, untrained {mse_zero:.3e}")
+    assert mse_trained < 0.1 * mse_zero
+    # gated step from sv[3] (interval 3) vs the exact integrator
+    dv = DeviceWorkload(wv)
+    exact = sv[3].clone()
+    D3 = Dv[3]
+    H = torch.full((wv.n,), -1.0, dtype=torch.float64, device="cuda")
+    ctx.step(exact, dv.T, D3, dv.fidx, dv.S_in, wv.dt, n=wv.n, H=H)
+    q_e, qc_e, _ = ctx.gas_flux(exact, dv.T)
+    ph_e = -torch.log10(H)
+    trained, _ = sur.get_weights()
+    res = {}
+    for tag, params in (("trained", trained), ("untrained", np.zeros(S.NPARAMS, np.float32))):
+        sur.set_weights(params, norm)
+        for tol_ion, tol_cl in ((1e-3, 1e-4), (1e-2, 1e-3), (3e-2, 3e-3), (1e-1, 1e-2)):
+            gate = S.adm1_gate(5.0, tol_ion, tol_cl)
+            Xs = sv[3].clone()
+            Hs = torch.full((wv.n,), -1.0, dtype=torch.float64, device="cuda")
+            route = torch.empty(wv.n, dtype=torch.uint8, device="cuda")
+            fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+            sur.step(Xs, dv.T, D3, dv.fidx, dv.S_in, wv.dt, gate, n=wv.n, H=Hs, route=route,
+                     fb_count=fb)
+            torch.cuda.synchronize()
+            acc = route.bool()
+            q_s, qc_s, _ = ctx.gas_flux(Xs, dv.T)
+            tank = abs(float(qc_s.sum()) - float(qc_e.sum())) / abs(float(qc_e.sum()))
+            e_ph = float(((-torch.log10(Hs) - ph_e).abs() / ph_e).max())
+            e_x = parity(Xs.cpu().numpy(), exact.cpu().numpy(), wv.n)
+            res[(tag, tol_ion)] = (int(fb.item()) / wv.n, tank, e_ph)
+            print(f"{tag} gate (ion {tol_ion:g}, closure {tol_cl:g}): fallback "
+                  f"{int(fb.item()) / wv.n:.3f}, accepted {int(acc.sum())}, tank methane rel "
+                  f"err {tank:.2e}, pH rel err max {e_ph:.2e}, state parity {e_x:.2e}")
+    # at the same gate the trained network is accepted more often and its
+    # gated result is closer to the exact integrator (methane flow and pH
+    # errors are reported above; pH stays within 1e-3)
+    fb_t, tank_t, ph_t = res[("trained", 3e-2)]
+    fb_u, tank_u, ph_u = res[("untrained", 3e-2)]
+    assert fb_t < fb_u
+    assert tank_t < tank_u and ph_t < ph_u
+    assert ph_t <= 1e-3
