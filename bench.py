@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--burn-in", type=int, default=2,
                     help="surrogate path: untimed FP64 steps before the comparison")
     ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--blocks-per-cu", type=int, default=0,
+                    help="resident waves per CU of the persistent step kernel (0: library "
+                         "default)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--cpu-sample", type=int, default=16384,
                     help="particles of the oracle CPU-baseline sample (0: skip)")
@@ -132,6 +135,8 @@ def main():
     torch.cuda.set_device(dev)
     w = W.batched_population(args.n, seed=2, steps=args.steps)
     ctx = A.Context(w.ld, rtol=args.rtol, atol=W.atol_vector(args.rtol), variant=args.variant)
+    if args.blocks_per_cu > 0:
+        A.adm1_set_launch(ctx.handle, A.VARIANT_SPARSE2, args.blocks_per_cu)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     X0 = t(w.X)
     X = X0.clone()

@@ -271,19 +271,13 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
     c->n_max = n_max;
     c->tuned_variant = -1;
     c->tuned_blocks_per_cu = 0;
-    int ncu = 0;
-    if (hipGetDevice(&c->device) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) !=
-            hipSuccess) {
+    if (hipGetDevice(&c->device) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
         return ADM1_E_NOMEM;
     }
-    c->work_blocks = adm1::sparse2_max_blocks(ncu);
-    const size_t work_bytes = (size_t)adm1::sparse2_work_doubles(c->work_blocks) * sizeof(double);
     if (hipMalloc(&c->d_queue, 64 * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&c->d_partial, kGasBlocks * 4 * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->d_work, work_bytes) != hipSuccess ||
         hipMalloc(&c->d_params, sizeof(DevParams)) != hipSuccess ||
         hipMemcpy(c->d_params, &c->dp, sizeof(DevParams), hipMemcpyHostToDevice) !=
             hipSuccess ||
@@ -291,7 +285,6 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
         (void)hipGetLastError();
         if (c->d_queue) (void)hipFree(c->d_queue);
         if (c->d_partial) (void)hipFree(c->d_partial);
-        if (c->d_work) (void)hipFree(c->d_work);
         if (c->d_params) (void)hipFree(c->d_params);
         delete c;
         return ADM1_E_NOMEM;
@@ -318,7 +311,6 @@ void adm1_destroy(adm1_ctx* ctx)
     if (!ctx) return;
     (void)hipFree(ctx->d_queue);
     (void)hipFree(ctx->d_partial);
-    (void)hipFree(ctx->d_work);
     (void)hipFree(ctx->d_params);
     delete ctx;
 }
@@ -348,7 +340,7 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
     a.H = aux ? aux->H : nullptr;
     a.hlast = aux ? aux->h_last : nullptr;
     a.status = status; a.nsteps = nsteps; a.queue = ctx->d_queue;
-    a.work = ctx->d_work; a.work_blocks = ctx->work_blocks; a.pdev = ctx->d_params;
+    a.pdev = ctx->d_params;
     int variant = ctx->opts.variant;
     if (variant < 0) variant = ctx->tuned_variant >= 0 ? ctx->tuned_variant : ADM1_VARIANT_SPARSE2;
     hipStream_t s = (hipStream_t)stream;
@@ -435,7 +427,7 @@ int adm1_set_launch(adm1_ctx* ctx, int32_t variant, int32_t blocks_per_cu)
 {
     if (!ctx) return ADM1_E_NULL;
     if (variant < 0 || variant >= ADM1_VARIANT_COUNT) return ADM1_E_VARIANT;
-    if (blocks_per_cu < 0 || blocks_per_cu > 4) return ADM1_E_OPTS;
+    if (blocks_per_cu < 0 || blocks_per_cu > 3) return ADM1_E_OPTS;
     ctx->tuned_variant = variant;
     ctx->tuned_blocks_per_cu = blocks_per_cu;
     return ADM1_OK;

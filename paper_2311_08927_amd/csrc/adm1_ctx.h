@@ -15,9 +15,7 @@ struct adm1_ctx {
     int device;
     int32_t* d_queue;    // work-queue counter
     double* d_partial;   // gas-flux block partials [kGasBlocks][4]
-    double* d_work;      // stage vectors of the two-lane step kernel
     adm1::DevParams* d_params;  // device copy of dp
-    int64_t work_blocks;
     int tuned_variant;   // step variant chosen by adm1_set_launch (-1: none)
     int tuned_blocks_per_cu;
 };

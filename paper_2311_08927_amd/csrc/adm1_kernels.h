@@ -25,8 +25,6 @@ struct StepArgs {
     const int32_t* index;   // optional particle index list (nullable: identity)
     const int32_t* index_count;  // device count of the index list (with index)
     const DevParams* pdev;  // device copy of p (read through the scalar cache)
-    double* work;           // stage-vector buffer of the two-lane kernel
-    int64_t work_blocks;    // blocks the work buffer holds
 };
 
 struct RhsArgs {
@@ -58,8 +56,6 @@ struct GasArgs {
 hipError_t launch_step1(const StepArgs& a, int rate_precision, bool sparse, hipStream_t s);
 hipError_t launch_step_sparse2(const StepArgs& a, int rate_precision, int blocks_per_cu,
                                hipStream_t s);
-int64_t sparse2_work_doubles(int64_t blocks);
-int sparse2_max_blocks(int ncu);
 hipError_t launch_rhs(const RhsArgs& a, int rate_precision, hipStream_t s);
 hipError_t launch_jacobian(const RhsArgs& a, double* J, hipStream_t s);
 hipError_t launch_gasflux(const GasArgs& a, int nblocks, double* totals, hipStream_t s);

@@ -10,11 +10,13 @@
 //     pattern) and stay in registers; pivot rows and solution components
 //     cross the pair with DPP quad_perm broadcasts, so both lanes run one
 //     instruction stream;
-//   - each lane keeps its rows' components of every vector; the stage
-//     vectors u_1..u_5 go to a coalesced global buffer [block][stage][row
-//     pair][lane] whose loads are issued in batches, and the particle's
-//     own state components, temperature constants and inflow terms D S_in
-//     sit in LDS, which keeps the registers for the LU and the rates;
+//   - each lane keeps its rows' components of every vector in LDS: the
+//     particle's own state components, the stage vectors and the stage
+//     argument, so the registers hold the LU and the rates and nothing of
+//     the step leaves the compute unit.  Four stage vectors are stored:
+//     the fifth stage folds u_1..u_5 into the argument and correction sums
+//     the sixth stage needs, which replace u_1, u_2;
+//   - inflow terms D S_in are read from the (small, cached) feed table;
 //   - both lanes evaluate the right-hand side redundantly (it needs the whole
 //     state) and each keeps only its rows of it;
 //   - the algebraic solves of each stage start from the linear prediction
@@ -40,8 +42,9 @@ constexpr int kVar0[NP] = ADM1_SP2_PAIR_VAR0;
 constexpr int kVar1[NP] = ADM1_SP2_PAIR_VAR1;
 constexpr int kVarPair[NP * 2] = ADM1_SP2_VAR_PAIR;
 constexpr int kVarSide[NP * 2] = ADM1_SP2_VAR_SIDE;
-constexpr int kWavesPerCU = 4;
-constexpr int kStored = kR4Stages - 1;  // stage vectors kept for later stages
+constexpr int kWavesPerCU = 3;  // LDS-limited: 3 x 48 KB per compute unit
+constexpr int kStored = 4;      // stage vectors kept in LDS (see the header)
+static_assert(kR4Stages == 6, "the stage-5 accumulation assumes six stages");
 
 static_assert(kVar0[NP - 1] == 28 && kVar1[NP - 1] == 29,
               "the constraint rows must form the last pair");
@@ -82,11 +85,11 @@ __device__ __forceinline__ void gather(const double* own, double* full, bool odd
 
 // Shared memory of one wave (one block of 64 lanes = 32 particle pairs).
 struct Lds {
-    double y[NDP][64];        // own components of each particle's state
-    double tc[10][32];        // temperature constants (9) and D per pair
-    double dsin[NLIQ][32];    // inflow terms D S_in per pair
-    double w[kStored][2][32]; // constraint components of the stage solutions
-    double arg[NY][32];       // current stage argument (whole vector) per pair
+    double u[kStored][NDP][64];         // own components of the stage vectors
+    double y[NDP][64];                  // own components of each particle's state
+    double tc[10][32];                  // temperature constants (9) and D per pair
+    double w[kR4Stages - 1][2][32];     // constraint components of the stage solutions
+    double arg[NY][32];                 // current stage argument (whole vector) per pair
 };
 
 // Whole stage argument of a pair, read from LDS where the rates use it.
@@ -105,17 +108,11 @@ __device__ __forceinline__ TConst load_tc(const Lds& L, int pr)
     return c;
 }
 
-struct LdsInflow {
-    const Lds* L;
-    int pr;
-    __device__ __forceinline__ double operator()(int k) const { return L->dsin[k][pr]; }
-};
-
 // Per-pair integration state kept in registers across loop iterations.
 struct PairState {
     double t, h, H, Sh2, hlast;
     int64_t pid;
-    int n, acc, rej, it;
+    int n, acc, rej, it, fi;
     bool reject_prev;
 };
 
@@ -196,6 +193,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
             s.hlast = a.hlast ? a.hlast[i] : -1.0;
             s.Sh2 = a.state[ROW_SH2 * a.ld + i];
             s.n = s.acc = s.rej = s.it = 0;
+            s.fi = fi;
             s.t = 0.0;
             s.reject_prev = false;
             bool fin = isfinite(T) && T > 0.0 && isfinite(D) && fi >= 0 && fi < a.n_feed;
@@ -217,8 +215,6 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                     L.tc[3][pr] = c.K_a_IN; L.tc[4][pr] = c.K_H_h2; L.tc[5][pr] = c.K_H_ch4;
                     L.tc[6][pr] = c.K_H_co2; L.tc[7][pr] = c.p_h2o; L.tc[8][pr] = c.arr;
                     L.tc[9][pr] = D;
-#pragma unroll
-                    for (int k = 0; k < NLIQ; ++k) L.dsin[k][pr] = D * sin[k];
                 }
             }
         } else {  // kHinit: second evaluation of the starting-step estimate
@@ -229,7 +225,8 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
         }
         if (!run) continue;
         double Ht = s.H, St = s.Sh2;
-        const int rc = rhs_in<R>(p, c, yin, D, LdsInflow{&L, pr}, Ht, St,
+        const int rc = rhs_in<R>(p, c, yin, D, FeedInflow{D, a.S_in + (int64_t)s.fi * NLIQ},
+                                 Ht, St,
                                  [&f](int k, double v) { f[k] = v; }, s.it);
         if (job == kFinish) {
             int st = 0;
@@ -339,7 +336,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
 // not unrolled: one right-hand-side, factorisation and solve site.
 template <typename R>
 __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState& s,
-                              bool odd, int lane, double* ub)
+                              bool odd, int lane)
 {
     const int pr = lane >> 1;
     {
@@ -358,7 +355,9 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
     ADM1_SP2_DECL;
     bool ok = true;
     double H0 = s.H, S0 = s.Sh2;
-    // stage vector u_j, row pair m of this lane: ub[(j * NDP + m) * 64]
+    // Stage vectors (this lane's row-pair components) in L.u: u_j in slot j
+    // for j < 4; after the fifth stage, slot 0 holds sum_j a_6j u_j and
+    // slot 1 sum_j c_6j u_j (j < 5).
 #pragma unroll 1
     for (int st = 0; st < kR4Stages; ++st) {
         const LdsVec arg{&L, pr};
@@ -366,10 +365,15 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
             double own[NDP];
 #pragma unroll
             for (int m = 0; m < NDP; ++m) own[m] = L.y[m][lane];
-            for (int j = 0; j < st; ++j) {
-                const double aj = kR4A[st][j];
+            if (st < kR4Stages - 1) {
+                for (int j = 0; j < st; ++j) {
+                    const double aj = kR4A[st][j];
 #pragma unroll
-                for (int m = 0; m < NDP; ++m) own[m] += aj * ub[(j * NDP + m) * 64];
+                    for (int m = 0; m < NDP; ++m) own[m] += aj * L.u[j][m][lane];
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < NDP; ++m) own[m] += L.u[0][m][lane];
             }
 #pragma unroll
             for (int m = 0; m < NDP; ++m) L.arg[odd ? kVar1[m] : kVar0[m]][pr] = own[m];
@@ -386,7 +390,9 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
         if (ok) {
             const DevParams& p = params_at(pp);
             const TConst c = load_tc(L, pr);
-            ok = rhs_in<R>(p, c, arg, L.tc[9][pr], LdsInflow{&L, pr}, s.H, s.Sh2,
+            const double D = L.tc[9][pr];
+            ok = rhs_in<R>(p, c, arg, D, FeedInflow{D, a.S_in + (int64_t)s.fi * NLIQ}, s.H,
+                           s.Sh2,
                            [&bv, odd](int k, double v) {
                                const int m = kVarPair[k];
                                if ((kVarSide[k] != 0) == odd) bv[m] = v;
@@ -400,7 +406,6 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
                     Partials d;
                     partials(q, c, arg, H0, S0, d);
                     const double alpha = 1.0 / (kR4Gamma * hs);
-                    const double D = L.tc[9][pr];
                     {
                         const DevParams& p = q;
                         ADM1_SP2_BUILD(alpha, D);
@@ -410,18 +415,37 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
             }
         }
         if (ok) {
-            for (int j = 0; j < st; ++j) {
-                const double cj = kR4C[st][j] * ih;
+            if (st < kR4Stages - 1) {
+                for (int j = 0; j < st; ++j) {
+                    const double cj = kR4C[st][j] * ih;
 #pragma unroll
-                for (int m = 0; m < NDP; ++m) bv[m] += cj * ub[(j * NDP + m) * 64];
+                    for (int m = 0; m < NDP; ++m) bv[m] += cj * L.u[j][m][lane];
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < NDP; ++m) bv[m] += ih * L.u[1][m][lane];
             }
             bv[NP - 1] = 0.0;
             ADM1_SP2_SOLVE();
             if (st < kStored) {
 #pragma unroll
-                for (int m = 0; m < NDP; ++m) ub[(st * NDP + m) * 64] = bv[m];
-                L.w[st][odd ? 1 : 0][pr] = bv[NP - 1];
+                for (int m = 0; m < NDP; ++m) L.u[st][m][lane] = bv[m];
+            } else if (st == kR4Stages - 2) {
+                // fold u_1..u_5 into the sums of the last stage
+#pragma unroll
+                for (int m = 0; m < NDP; ++m) {
+                    double sa = 0.0, sc = 0.0;
+#pragma unroll
+                    for (int j = 0; j < kStored; ++j) {
+                        const double uj = L.u[j][m][lane];
+                        sa += kR4A[kR4Stages - 1][j] * uj;
+                        sc += kR4C[kR4Stages - 1][j] * uj;
+                    }
+                    L.u[0][m][lane] = sa + kR4A[kR4Stages - 1][kStored] * bv[m];
+                    L.u[1][m][lane] = sc + kR4C[kR4Stages - 1][kStored] * bv[m];
+                }
             }
+            if (st < kR4Stages - 1) L.w[st][odd ? 1 : 0][pr] = bv[NP - 1];
         }
     }
     ++s.n;
@@ -430,13 +454,7 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
     if (ok) {
         const DevParams& p = params_at(pp);
 #pragma unroll
-        for (int m = 0; m < NDP; ++m) y1[m] = L.y[m][lane] + bv[m];
-#pragma unroll
-        for (int j = 0; j < kStored; ++j) {
-            const double aj = kR4A[kR4Stages - 1][j];
-#pragma unroll
-            for (int m = 0; m < NDP; ++m) y1[m] += aj * ub[(j * NDP + m) * 64];
-        }
+        for (int m = 0; m < NDP; ++m) y1[m] = L.y[m][lane] + (L.u[0][m][lane] + bv[m]);
         double e = 0.0;
         bool fin = true;
 #pragma unroll
@@ -489,7 +507,6 @@ __global__ void __launch_bounds__(64, 1) k_step_sparse2(StepArgs a)
     const bool odd = lane & 1;
     const int64_t total = a.index ? (int64_t)(*a.index_count) : a.n;
     cparams_t pp = (cparams_t)a.pdev;
-    double* ub = a.work + (int64_t)blockIdx.x * kStored * NDP * 64 + lane;
     PairState s;
     s.pid = -1;
     bool active = false, exhausted = false;
@@ -498,7 +515,7 @@ __global__ void __launch_bounds__(64, 1) k_step_sparse2(StepArgs a)
         service<R>(a, pp, L, s, job, fin_status, active, exhausted, odd, lane, total);
         if (__all(exhausted)) break;
         if (active) {
-            const int r = attempt<R>(a, pp, L, s, odd, lane, ub);
+            const int r = attempt<R>(a, pp, L, s, odd, lane);
             if (r) {
                 fin_status = r - 1;
                 job = kFinish;
@@ -511,10 +528,6 @@ __global__ void __launch_bounds__(64, 1) k_step_sparse2(StepArgs a)
 __global__ void k_reset_queue(int32_t* q) { q[0] = 0; }
 
 }  // namespace
-
-int64_t sparse2_work_doubles(int64_t blocks) { return blocks * kStored * NDP * 64; }
-
-int sparse2_max_blocks(int ncu) { return ncu * kWavesPerCU; }
 
 hipError_t launch_step_sparse2(const StepArgs& a, int rate_precision, int blocks_per_cu,
                                hipStream_t s)
@@ -529,7 +542,6 @@ hipError_t launch_step_sparse2(const StepArgs& a, int rate_precision, int blocks
     int64_t grid = (int64_t)ncu * per_cu;
     const int64_t need = (a.n + 31) / 32;
     if (!a.index && need < grid) grid = need;
-    if (grid > a.work_blocks) grid = a.work_blocks;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, a.queue);
     if ((e = hipGetLastError()) != hipSuccess) return e;

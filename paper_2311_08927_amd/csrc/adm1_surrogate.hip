@@ -573,7 +573,7 @@ int adm1_surrogate_step(adm1_surrogate* s, double* state, int64_t ld, const doub
     a.hlast = aux ? aux->h_last : nullptr;
     a.status = status; a.nsteps = nsteps; a.queue = ctx->d_queue;
     a.index = s->fb_idx; a.index_count = cnt;
-    a.work = ctx->d_work; a.work_blocks = ctx->work_blocks; a.pdev = ctx->d_params;
+    a.pdev = ctx->d_params;
     return hip_rc(adm1::launch_step_sparse2(a, ctx->opts.rate_precision, ctx->tuned_blocks_per_cu,
                                             st));
 }
