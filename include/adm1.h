@@ -200,8 +200,8 @@ int adm1_jacobian(adm1_ctx *ctx, const double *state, int64_t ld, const double *
 
 /* Launch configuration of the step kernel used when opts.variant is -1:
  * variant (an ADM1_VARIANT_* value) and, for ADM1_VARIANT_SPARSE2, resident
- * blocks (waves) per compute unit of the persistent grid (1..3; 0 = 3, the
- * most that fit the kernel's 48 KB of LDS per wave).
+ * blocks (waves) per compute unit of the persistent grid (1..4; 0 = 4, one
+ * per SIMD, the most that fit the kernel's 40 KB of LDS per wave).
  * Set by the autotuner after timing the candidates.  Synchronous. */
 int adm1_set_launch(adm1_ctx *ctx, int32_t variant, int32_t blocks_per_cu);
 

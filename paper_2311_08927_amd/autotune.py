@@ -17,7 +17,7 @@ import numpy as np
 
 from . import adm1 as A
 
-CANDIDATES = [(A.VARIANT_SPARSE1, 0)] + [(A.VARIANT_SPARSE2, b) for b in (1, 2, 3)]
+CANDIDATES = [(A.VARIANT_SPARSE1, 0)] + [(A.VARIANT_SPARSE2, b) for b in (1, 2, 3, 4)]
 CACHE = os.environ.get("ADM1_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "adm1_autotune.json"))
 

@@ -427,7 +427,7 @@ int adm1_set_launch(adm1_ctx* ctx, int32_t variant, int32_t blocks_per_cu)
 {
     if (!ctx) return ADM1_E_NULL;
     if (variant < 0 || variant >= ADM1_VARIANT_COUNT) return ADM1_E_VARIANT;
-    if (blocks_per_cu < 0 || blocks_per_cu > 3) return ADM1_E_OPTS;
+    if (blocks_per_cu < 0 || blocks_per_cu > 4) return ADM1_E_OPTS;
     ctx->tuned_variant = variant;
     ctx->tuned_blocks_per_cu = blocks_per_cu;
     return ADM1_OK;

@@ -10,12 +10,13 @@
 //     pattern) and stay in registers; pivot rows and solution components
 //     cross the pair with DPP quad_perm broadcasts, so both lanes run one
 //     instruction stream;
-//   - each lane keeps its rows' components of every vector in LDS: the
-//     particle's own state components, the stage vectors and the stage
-//     argument, so the registers hold the LU and the rates and nothing of
-//     the step leaves the compute unit.  Four stage vectors are stored:
-//     the fifth stage folds u_1..u_5 into the argument and correction sums
-//     the sixth stage needs, which replace u_1, u_2;
+//   - each lane keeps its rows' components of the stage vectors and the
+//     pair's whole stage argument in LDS (40 KB per wave, so four waves,
+//     one per SIMD, fit a compute unit) and its rows of the state in
+//     registers; the LU and the rates fill the rest of the registers (what
+//     still spills is the only per-step memory traffic).  Four stage
+//     vectors are stored: the fifth stage folds u_1..u_5 into the argument
+//     and correction sums the sixth stage needs, which replace u_1, u_2;
 //   - inflow terms D S_in are read from the (small, cached) feed table;
 //   - both lanes evaluate the right-hand side redundantly (it needs the whole
 //     state) and each keeps only its rows of it;
@@ -42,7 +43,7 @@ constexpr int kVar0[NP] = ADM1_SP2_PAIR_VAR0;
 constexpr int kVar1[NP] = ADM1_SP2_PAIR_VAR1;
 constexpr int kVarPair[NP * 2] = ADM1_SP2_VAR_PAIR;
 constexpr int kVarSide[NP * 2] = ADM1_SP2_VAR_SIDE;
-constexpr int kWavesPerCU = 3;  // LDS-limited: 3 x 48 KB per compute unit
+constexpr int kWavesPerCU = 4;  // one wave per SIMD: 4 x 40 KB of LDS per CU
 constexpr int kStored = 4;      // stage vectors kept in LDS (see the header)
 static_assert(kR4Stages == 6, "the stage-5 accumulation assumes six stages");
 
@@ -86,7 +87,6 @@ __device__ __forceinline__ void gather(const double* own, double* full, bool odd
 // Shared memory of one wave (one block of 64 lanes = 32 particle pairs).
 struct Lds {
     double u[kStored][NDP][64];         // own components of the stage vectors
-    double y[NDP][64];                  // own components of each particle's state
     double tc[10][32];                  // temperature constants (9) and D per pair
     double w[kR4Stages - 1][2][32];     // constraint components of the stage solutions
     double arg[NY][32];                 // current stage argument (whole vector) per pair
@@ -114,6 +114,7 @@ struct PairState {
     int64_t pid;
     int n, acc, rej, it, fi;
     bool reject_prev;
+    double y[NDP];  // own components of the particle's state
 };
 
 enum Job { kNone = 0, kFinish = 1, kStart = 2, kHinit = 3 };
@@ -178,7 +179,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
             } else {
                 double own[NDP];
 #pragma unroll
-                for (int m = 0; m < NDP; ++m) own[m] = L.y[m][lane];
+                for (int m = 0; m < NDP; ++m) own[m] = s.y[m];
                 gather(own, yin, odd);
             }
             c = load_tc(L, pr);
@@ -237,7 +238,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
 #pragma unroll
                 for (int m = 0; m < NDP; ++m) {
                     const int k = odd ? kVar1[m] : kVar0[m];
-                    a.state[state_row(k) * a.ld + i] = L.y[m][lane];
+                    a.state[state_row(k) * a.ld + i] = s.y[m];
                 }
                 if (!odd) {
                     a.state[ROW_SH2 * a.ld + i] = St;
@@ -267,7 +268,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                 s.Sh2 = St;
 #pragma unroll
                 for (int m = 0; m < NDP; ++m)
-                    L.y[m][lane] = odd ? yin[kVar1[m]] : yin[kVar0[m]];
+                    s.y[m] = odd ? yin[kVar1[m]] : yin[kVar0[m]];
                 if (s.hlast > 0.0) {
                     s.h = fmin(a.dt, s.hlast);
                     active = true;
@@ -364,7 +365,7 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
         {
             double own[NDP];
 #pragma unroll
-            for (int m = 0; m < NDP; ++m) own[m] = L.y[m][lane];
+            for (int m = 0; m < NDP; ++m) own[m] = s.y[m];
             if (st < kR4Stages - 1) {
                 for (int j = 0; j < st; ++j) {
                     const double aj = kR4A[st][j];
@@ -454,13 +455,13 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
     if (ok) {
         const DevParams& p = params_at(pp);
 #pragma unroll
-        for (int m = 0; m < NDP; ++m) y1[m] = L.y[m][lane] + (L.u[0][m][lane] + bv[m]);
+        for (int m = 0; m < NDP; ++m) y1[m] = s.y[m] + (L.u[0][m][lane] + bv[m]);
         double e = 0.0;
         bool fin = true;
 #pragma unroll
         for (int m = 0; m < NDP; ++m) {
             const double at = odd ? p.atol[kVar1[m]] : p.atol[kVar0[m]];
-            const double sc = at + p.rtol * fmax(fabs(L.y[m][lane]), fabs(y1[m]));
+            const double sc = at + p.rtol * fmax(fabs(s.y[m]), fabs(y1[m]));
             e += (bv[m] / sc) * (bv[m] / sc);
             fin = fin && isfinite(y1[m]);
         }
@@ -474,7 +475,7 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
     if (ok && err <= 1.0) {
         ++s.acc;
 #pragma unroll
-        for (int m = 0; m < NDP; ++m) L.y[m][lane] = y1[m];
+        for (int m = 0; m < NDP; ++m) s.y[m] = y1[m];
         // algebraic warm start for the next step: the stage-6 roots plus the
         // linear correction of the last stage
         const double wHl = bc0(bv[NP - 1]), wSl = bc1(bv[NP - 1]);
