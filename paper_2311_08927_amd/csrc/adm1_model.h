@@ -36,6 +36,19 @@ __host__ __device__ constexpr int state_row(int k)
 
 #include "adm1_partials.inc"
 
+// Reciprocal of a finite non-zero x: the hardware estimate refined by two
+// Newton-Raphson steps (the error squares at each step, so the estimate's
+// error falls far below the FP64 rounding).
+__device__ __forceinline__ double frcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float frcp(float x) { return 1.0f / x; }
+
 struct TConst {
     double RT, K_w, K_a_co2, K_a_IN, K_H_h2, K_H_ch4, K_H_co2, p_h2o, arr;
 };
@@ -65,10 +78,10 @@ template <typename Y>
 __device__ __forceinline__ double charge_balance(const DevParams& p, const TConst& c,
                                                  const Y& y, double H, double& dE)
 {
-    const double iIN = 1.0 / (c.K_a_IN + H), iCO2 = 1.0 / (c.K_a_co2 + H);
-    const double iac = 1.0 / (p.K_a_ac + H), ipro = 1.0 / (p.K_a_pro + H);
-    const double ibu = 1.0 / (p.K_a_bu + H), iva = 1.0 / (p.K_a_va + H);
-    const double iH = 1.0 / H;
+    const double iIN = frcp(c.K_a_IN + H), iCO2 = frcp(c.K_a_co2 + H);
+    const double iac = frcp(p.K_a_ac + H), ipro = frcp(p.K_a_pro + H);
+    const double ibu = frcp(p.K_a_bu + H), iva = frcp(p.K_a_va + H);
+    const double iH = frcp(H);
     const double nh3 = c.K_a_IN * y[SIN] * iIN;
     const double hco3 = c.K_a_co2 * y[SIC] * iCO2;
     const double ac = p.K_a_ac * y[Sac] * iac * (1.0 / 64.0);
@@ -94,7 +107,7 @@ __device__ __forceinline__ int solve_H(const DevParams& p, const TConst& c, cons
         double dE;
         const double E = charge_balance(p, c, y, h, dE);
         if (!isfinite(E) || !isfinite(dE)) return 1;
-        double hn = h - E / dE;
+        double hn = h - E * frcp(dE);
         if (!(hn >= 0.1 * h)) hn = 0.1 * h;
         else if (hn > 10.0 * h) hn = 10.0 * h;
         ++iters;
@@ -123,8 +136,8 @@ struct H2Terms {
 __device__ __forceinline__ double h2_balance(const DevParams& p, const H2Terms& t, double D,
                                              double S, double& dE)
 {
-    const double ifa = 1.0 / (p.K_I_h2_fa + S), ic4 = 1.0 / (p.K_I_h2_c4 + S);
-    const double ipro = 1.0 / (p.K_I_h2_pro + S), ih2 = 1.0 / (p.K_S_h2 + S);
+    const double ifa = frcp(p.K_I_h2_fa + S), ic4 = frcp(p.K_I_h2_c4 + S);
+    const double ipro = frcp(p.K_I_h2_pro + S), ih2 = frcp(p.K_S_h2 + S);
     const double a7 = t.c7 * p.K_I_h2_fa * ifa, a8 = t.c8 * p.K_I_h2_c4 * ic4;
     const double a10 = t.c10 * p.K_I_h2_pro * ipro;
     dE = -(D + p.kLa) - a7 * ifa - a8 * ic4 - a10 * ipro - t.c12 * p.K_S_h2 * ih2 * ih2;
@@ -141,7 +154,7 @@ __device__ __forceinline__ int solve_Sh2(const DevParams& p, const H2Terms& t, d
         double dE;
         const double E = h2_balance(p, t, D, s, dE);
         if (!isfinite(E) || !isfinite(dE)) return 1;
-        double sn = s - E / dE;
+        double sn = s - E * frcp(dE);
         if (!(sn > lo)) sn = 0.5 * (s + lo);
         ++iters;
         const bool done = fabs(sn - s) <= p.newton_qtol * fabs(sn) + 1e-30;
@@ -165,7 +178,7 @@ __device__ __forceinline__ R inhib_pH(R H, double K, double n, int nint)
     else if (nint == 3) rn = r * r * r;
     else if (nint == 4) { const R r2 = r * r; rn = r2 * r2; }
     else rn = exp2((R)n * log2(r));
-    return (R)1 / ((R)1 + rn);
+    return frcp((R)1 + rn);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,9 +214,9 @@ __device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const
     const R I_ac = inhib_pH<R>(Hr, p.pH_K[1], p.pH_n[1], p.pH_nint[1]);
     const R I_h2 = inhib_pH<R>(Hr, p.pH_K[2], p.pH_n[2], p.pH_nint[2]);
     const R sIN = (R)y[SIN];
-    const R I_IN = sIN / (sIN + (R)p.K_S_IN);                       // eq. 6
-    const R nh3 = (R)c.K_a_IN * sIN / ((R)c.K_a_IN + Hr);
-    const R I_nh3 = (R)1 / ((R)1 + nh3 / (R)p.K_I_nh3);             // eq. 5
+    const R I_IN = sIN * frcp(sIN + (R)p.K_S_IN);                       // eq. 6
+    const R nh3 = (R)c.K_a_IN * sIN * frcp((R)c.K_a_IN + Hr);
+    const R I_nh3 = frcp((R)1 + nh3 * (R)(1.0 / p.K_I_nh3));            // eq. 5
     const R I5 = I_aa * I_IN;
 
     R rho[19];
@@ -213,23 +226,23 @@ __device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const
     rho[3] = a * (R)p.k_hyd_li * (R)y[Xli];
     {
         const R s = (R)y[Ssu];
-        rho[4] = a * (R)p.k_m_su * s / ((R)p.K_S_su + s) * (R)y[Xsu] * I5;
+        rho[4] = a * (R)p.k_m_su * s * frcp((R)p.K_S_su + s) * (R)y[Xsu] * I5;
     }
     {
         const R s = (R)y[Saa];
-        rho[5] = a * (R)p.k_m_aa * s / ((R)p.K_S_aa + s) * (R)y[Xaa] * I5;
+        rho[5] = a * (R)p.k_m_aa * s * frcp((R)p.K_S_aa + s) * (R)y[Xaa] * I5;
     }
     const R sfa = (R)y[Sfa];
-    const R b7 = a * (R)p.k_m_fa * sfa / ((R)p.K_S_fa + sfa) * (R)y[Xfa] * I5;
+    const R b7 = a * (R)p.k_m_fa * sfa * frcp((R)p.K_S_fa + sfa) * (R)y[Xfa] * I5;
     const R sva = (R)y[Sva], sbu = (R)y[Sbu];
-    const R isum = (R)1 / (sva + sbu + (R)p.eps_c4);
-    const R b8 = a * (R)p.k_m_c4 * sva / ((R)p.K_S_c4 + sva) * (R)y[Xc4] * sva * isum * I5;
-    const R b9 = a * (R)p.k_m_c4 * sbu / ((R)p.K_S_c4 + sbu) * (R)y[Xc4] * sbu * isum * I5;
+    const R isum = frcp(sva + sbu + (R)p.eps_c4);
+    const R b8 = a * (R)p.k_m_c4 * sva * frcp((R)p.K_S_c4 + sva) * (R)y[Xc4] * sva * isum * I5;
+    const R b9 = a * (R)p.k_m_c4 * sbu * frcp((R)p.K_S_c4 + sbu) * (R)y[Xc4] * sbu * isum * I5;
     const R spro = (R)y[Spro];
-    const R b10 = a * (R)p.k_m_pro * spro / ((R)p.K_S_pro + spro) * (R)y[Xpro] * I5;
+    const R b10 = a * (R)p.k_m_pro * spro * frcp((R)p.K_S_pro + spro) * (R)y[Xpro] * I5;
     {
         const R s = (R)y[Sac];
-        rho[10] = a * (R)p.k_m_ac * s / ((R)p.K_S_ac + s) * (R)y[Xac] * I_ac * I_IN * I_nh3;
+        rho[10] = a * (R)p.k_m_ac * s * frcp((R)p.K_S_ac + s) * (R)y[Xac] * I_ac * I_IN * I_nh3;
     }
     const R b12 = a * (R)p.k_m_h2 * (R)y[Xh2] * I_h2 * I_IN;
 #pragma unroll
@@ -245,17 +258,18 @@ __device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const
     t.kh = c.K_H_h2 * c.RT * y[Gh2];
     if (solve_Sh2(p, t, D, Sh2, iters)) return 1;
     const R S = (R)Sh2;
-    rho[6] = b7 * (R)p.K_I_h2_fa / ((R)p.K_I_h2_fa + S);
-    rho[7] = b8 * (R)p.K_I_h2_c4 / ((R)p.K_I_h2_c4 + S);
-    rho[8] = b9 * (R)p.K_I_h2_c4 / ((R)p.K_I_h2_c4 + S);
-    rho[9] = b10 * (R)p.K_I_h2_pro / ((R)p.K_I_h2_pro + S);
-    rho[11] = b12 * S / ((R)p.K_S_h2 + S);
+    rho[6] = b7 * (R)p.K_I_h2_fa * frcp((R)p.K_I_h2_fa + S);
+    const R ic4 = (R)p.K_I_h2_c4 * frcp((R)p.K_I_h2_c4 + S);
+    rho[7] = b8 * ic4;
+    rho[8] = b9 * ic4;
+    rho[9] = b10 * (R)p.K_I_h2_pro * frcp((R)p.K_I_h2_pro + S);
+    rho[11] = b12 * S * frcp((R)p.K_S_h2 + S);
 
     // liquid-gas transfer and headspace outflow
     const R kLa = (R)p.kLa;
     const R T8 = kLa * (S - (R)t.kh);
     const R T9 = kLa * ((R)y[Sch4] - (R)(c.K_H_ch4 * c.RT) * (R)y[Gch4]);
-    const R co2 = (R)y[SIC] * Hr / ((R)c.K_a_co2 + Hr);
+    const R co2 = (R)y[SIC] * Hr * frcp((R)c.K_a_co2 + Hr);
     const R T10 = kLa * (co2 - (R)(c.K_H_co2 * c.RT) * (R)y[Gco2]);
     const R P = (R)c.RT * ((R)y[Gh2] * (R)(1.0 / 16.0) + (R)y[Gch4] * (R)(1.0 / 64.0) +
                            (R)y[Gco2]) + (R)c.p_h2o;

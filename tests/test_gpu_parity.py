@@ -121,6 +121,54 @@ def test_step_parity_cstr(torch_cuda, orc, variant):
     assert worst <= PARITY_TOL
 
 
+def test_step_parity_cstr_full_day(torch_cuda, orc):
+    """The whole CSTR population: 256 particles, 96 coupling intervals of
+    1/96 d (one simulated day), parity checked at every interval end."""
+    w = W.cstr_population(256, seed=1)
+    ctx = make_ctx(w.ld)
+    worst, xg, xo, stg, sto, cg, co = run_side_by_side(ctx, orc, w, steps=96,
+                                                       nthreads=None)
+    print(f"full day: parity {worst:.3e} over 96 intervals; accepted steps in the last "
+          f"interval gpu/oracle {cg[0, :w.n].sum()}/{co[0, :w.n].sum()}")
+    assert (stg & 0x7F == 0).all() and (sto & 0x7F == 0).all()
+    assert worst <= PARITY_TOL
+
+
+def test_steady_state(torch_cuda, orc):
+    """At the oracle's CSTR steady state of the nominal reactor the GPU
+    right-hand side vanishes to 1e-10 of the flux scale, and one simulated
+    day of GPU integration stays within 1e-8 of it."""
+    import torch
+    nom = W.nominal()
+    x = nom["state"]
+    n, ld = 64, 64
+    X = np.repeat(x[:, None], ld, axis=1)
+    T = np.full(n, nom["T"])
+    D = np.full(n, nom["D"])
+    feed = np.ascontiguousarray(nom["feed"][None, :])
+    fidx = np.zeros(n, dtype=np.int32)
+    ctx = make_ctx(ld)
+    dX = torch.from_numpy(X).cuda()
+    dT, dD = torch.from_numpy(T).cuda(), torch.from_numpy(D).cuda()
+    dS, dfi = torch.from_numpy(feed).cuda(), torch.from_numpy(fidx).cuda()
+    f, _, st = ctx.rhs(dX, dT, dD, dfi, dS, n=n)
+    f = f.cpu().numpy()[:, :n]
+    # flux scale of each entry: its dilution exchange D |x|
+    rel = np.max(np.abs(f) / (D[0] * np.abs(x[np.array(DIFF)])[:, None]))
+    print(f"steady state: max |f| / (D |x|) = {rel:.3e}")
+    assert (st.cpu().numpy() == 0).all()
+    assert rel <= 1e-10
+    H = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+    hl = H.clone()
+    for _ in range(96):
+        ctx.step(dX, dT, dD, dfi, dS, 1.0 / 96, n=n, H=H, hlast=hl)
+    xe = dX.cpu().numpy()[:, :n]
+    drift = np.max(np.abs(xe - x[:, None]) / np.maximum(np.abs(x[:, None]),
+                                                       1e-4 * x[:, None]))
+    print(f"steady state: drift over one day {drift:.3e}")
+    assert drift <= 1e-8
+
+
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_step_parity_batched_subset(torch_cuda, orc, variant):
     """Batched population (per-particle temperature, pulsed feed zone): a
