@@ -335,7 +335,8 @@ int adm1_surrogate_featurize(adm1_surrogate *s, const double *state, int64_t ld,
 int adm1_surrogate_targets(adm1_surrogate *s, const double *x0, const double *x1, int64_t ld,
                            int64_t n, float *target, void *stream);
 
-/* Network outputs Y = float32 [n][48] for inputs X = BF16 [n][64]. */
+/* Network outputs Y = float32 [n][48] for inputs X = BF16 [n][64] (X
+ * 16-byte aligned, else ADM1_E_SIZE). */
 int adm1_surrogate_forward(adm1_surrogate *s, const uint16_t *X, int64_t n, float *Y,
                            void *stream);
 

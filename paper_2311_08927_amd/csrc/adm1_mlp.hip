@@ -3,16 +3,18 @@
 // the log-space increments of its 35 entries over one coupling interval.
 //
 // Network 38 -> 256 -> 256 -> 256 -> 256 -> 35, GELU (erf form), BF16
-// weights and activations, FP32 accumulation on the matrix cores
-// (v_mfma_f32_16x16x16_bf16), FP32 master weights and Adam.
+// weights and activations, FP32 accumulation on the matrix cores, FP32
+// master weights and Adam.
 //
 // Kernels:
-//   k_mlp_fwd    fused forward: a 128-row tile stays in LDS for all five
-//                layers (two 128 x 264 BF16 buffers), weights stream from L2
-//                in the transposed layout WT[out][in] so each lane's four
-//                k-values are contiguous; optional saving of pre-activations
-//                (FP32) and activations (BF16) for the backward pass;
-//   k_gemm       generic strided BF16 GEMM with LDS staging and split-K,
+//   k_mlp_fwd    fused forward (v_mfma_f32_16x16x32_bf16): a 64-row tile
+//                stays in LDS for all five layers (two 64 x 264 BF16
+//                buffers), weights stream from L2 in the transposed layout
+//                WT[out][in] so each lane's eight k-values are one 16-byte
+//                load; optional saving of pre-activations (FP32) and
+//                activations (BF16) for the backward pass;
+//   k_gemm       generic strided BF16 GEMM (v_mfma_f32_16x16x16_bf16) with
+//                LDS staging and split-K,
 //                used by the backward pass (dH = dZ W^T, dW = H^T dZ);
 //   k_loss, k_gelu_bwd, k_colsum, k_splitk_sum, k_adam, k_pack: the
 //                elementwise and reduction steps of training;
@@ -55,14 +57,29 @@ __device__ __forceinline__ f32x4 mfma16(s16x4 a, s16x4 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
 // ---------------------------------------------------------------------------
-// Fused forward.  MFMA 16x16x16 operand layout (lane l of 64):
-//   A (16 x 16, rows i, k):  row l % 16, k = 4 (l / 16) + t, t = 0..3
-//   B (16 x 16, k, cols j):  col l % 16, k = 4 (l / 16) + t
-//   C (16 x 16):             col l % 16, rows 4 (l / 16) + t
+// Fused forward on gfx950's 16x16x32 BF16 MFMA.  Operand layout (lane l):
+//   A (16 x 32, rows i, k):  row l % 16, k = 8 (l / 16) + t, t = 0..7
+//   B (32 x 16, k, cols j):  col l % 16, k = 8 (l / 16) + t
+//   C (16 x 16):             col l % 16, rows 4 (l / 16) + t, t = 0..3
+// A block of 256 threads owns 64 rows; the activations of all five layers
+// stay in two 64 x 264 BF16 LDS buffers (67.6 KB: two blocks per CU).
+// Wave w owns the column tiles [w CTW, (w + 1) CTW) of a layer and all four
+// row tiles; each lane's eight k-values of a weight column are one 16-byte
+// load from W^T, issued one k-step ahead of the MFMAs that use them.
 // ---------------------------------------------------------------------------
-constexpr int TM = 128;      // rows per block
-constexpr int LDH = 264;     // LDS row stride (BF16 elements), padded
+constexpr int TM = 64;       // rows per block
+constexpr int RT = TM / 16;  // row tiles
+constexpr int LDH = 264;     // LDS row stride (BF16 elements): 528 B, 16-byte aligned
 constexpr int kThreads = 256;
 
 struct FwdArgs {
@@ -75,8 +92,7 @@ struct FwdArgs {
     uint16_t* hsave[4];  // [n][256] BF16 activations (nullable)
 };
 
-// One layer: out[TM][NOUT] = act(in[TM][K] W + b).  Wave w owns column
-// tiles; every wave covers all 8 row tiles.
+// One layer: out[TM][NOUT] = act(in[TM][K] W + b).
 template <int K, int NOUT, bool LAST>
 __device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const uint16_t* in,
                                           uint16_t* out, int64_t row0)
@@ -84,42 +100,49 @@ __device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const uin
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     constexpr int CT = NOUT / 16;                 // column tiles
     constexpr int CTW = (CT + 3) / 4;             // per wave
+    constexpr int KS = K / 32;                    // k-steps
     const int c0 = w * CTW;
-    f32x4 acc[8][CTW];
+    f32x4 acc[RT][CTW];
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int c = 0; c < CTW; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint16_t* WT = a.WT[layer];
-    const int kq = 4 * (lane >> 4), li = lane & 15;
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        s16x4 bf[CTW];
+    const int kq = 8 * (lane >> 4), li = lane & 15;
+    s16x8 bnext[CTW];
+#pragma unroll
+    for (int c = 0; c < CTW; ++c)
+        bnext[c] = (c0 + c < CT) ? *(const s16x8*)(WT + (int64_t)((c0 + c) * 16 + li) * K + kq)
+                                 : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k0 = ks * 32;
+        s16x8 bf[CTW];
 #pragma unroll
         for (int c = 0; c < CTW; ++c) {
-            const int col = (c0 + c) * 16 + li;
-            if (c0 + c < CT)
-                bf[c] = *(const s16x4*)(WT + (int64_t)col * K + k0 + kq);
-            else
-                bf[c] = s16x4{0, 0, 0, 0};
+            bf[c] = bnext[c];
+            if (ks + 1 < KS && c0 + c < CT)
+                bnext[c] = *(const s16x8*)(WT + (int64_t)((c0 + c) * 16 + li) * K + k0 + 32 + kq);
         }
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const s16x4 af = *(const s16x4*)(in + (r * 16 + li) * LDH + k0 + kq);
+        for (int r = 0; r < RT; ++r) {
+            const s16x8 af = *(const s16x8*)(in + (r * 16 + li) * LDH + k0 + kq);
 #pragma unroll
-            for (int c = 0; c < CTW; ++c) acc[r][c] = mfma16(af, bf[c], acc[r][c]);
+            for (int c = 0; c < CTW; ++c) acc[r][c] = mfma32(af, bf[c], acc[r][c]);
         }
     }
     const float* bias = a.b[layer];
+    const int rq = 4 * (lane >> 4);
 #pragma unroll
     for (int c = 0; c < CTW; ++c) {
         if (c0 + c >= CT) continue;
         const int col = (c0 + c) * 16 + li;
         const float bc = bias[col];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < RT; ++r) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int row = r * 16 + kq + t;
+                const int row = r * 16 + rq + t;
                 const int64_t grow = row0 + row;
                 const float z = acc[r][c][t] + bc;
                 if (LAST) {
@@ -140,16 +163,16 @@ __device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const uin
 
 __global__ void __launch_bounds__(kThreads) k_mlp_fwd(FwdArgs a)
 {
-    __shared__ uint16_t buf0[TM * LDH];
-    __shared__ uint16_t buf1[TM * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t buf0[TM * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t buf1[TM * LDH];
     const int64_t row0 = (int64_t)blockIdx.x * TM;
-    // input tile: 128 rows x 64 features (8 bytes per load)
-    for (int e = threadIdx.x; e < TM * 16; e += kThreads) {
-        const int row = e >> 4, q = (e & 15) * 4;
+    // input tile: 64 rows x 64 features, 16 bytes per load
+    for (int e = threadIdx.x; e < TM * 8; e += kThreads) {
+        const int row = e >> 3, q = (e & 7) * 8;
         const int64_t grow = row0 + row;
-        s16x4 v = s16x4{0, 0, 0, 0};
-        if (grow < a.n) v = *(const s16x4*)(a.X + grow * 64 + q);
-        *(s16x4*)(buf0 + row * LDH + q) = v;
+        s16x8 v = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (grow < a.n) v = *(const s16x8*)(a.X + grow * 64 + q);
+        *(s16x8*)(buf0 + row * LDH + q) = v;
     }
     __syncthreads();
     fwd_layer<64, 256, false>(a, 0, buf0, buf1, row0);

@@ -494,7 +494,7 @@ int adm1_surrogate_forward(adm1_surrogate* s, const uint16_t* X, int64_t n, floa
     int rc = check_surrogate(s);
     if (rc) return rc;
     if (!X || !Y) return ADM1_E_NULL;
-    if (n < 0) return ADM1_E_SIZE;
+    if (n < 0 || ((uintptr_t)X & 15) != 0) return ADM1_E_SIZE;
     if (!is_device(X) || !is_device(Y)) return ADM1_E_NOT_DEVICE;
     return hip_rc(mlp_forward(mlp_dev(s, false), X, n, Y, false, (hipStream_t)stream));
 }
