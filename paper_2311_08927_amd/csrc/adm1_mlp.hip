@@ -30,12 +30,13 @@ namespace {
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// FP32 -> BF16, round to nearest even; NaN stays a (quiet) NaN.
 __device__ __forceinline__ uint16_t f2bf(float x)
 {
-    uint32_t u = __builtin_bit_cast(uint32_t, x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t q = (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+    return (uint16_t)(((u & 0x7f800000u) == 0x7f800000u) ? q : r);
 }
 __device__ __forceinline__ float bf2f(uint16_t b)
 {
@@ -66,16 +67,35 @@ __device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c)
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// GELU with a branch-free erf: Abramowitz & Stegun, Handbook of
+// Mathematical Functions, eq. 7.1.26 (|error| <= 1.5e-7 on the real line),
+// odd extension to negative arguments.
+__device__ __forceinline__ float gelu_fast(float z)
+{
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+    const float poly =
+        t * (0.254829592f +
+             t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+    const float erf_abs = 1.0f - poly * __expf(-x * x);
+    const float erf_z = copysignf(erf_abs, z);
+    return 0.5f * z * (1.0f + erf_z);
+}
+
 // ---------------------------------------------------------------------------
 // Fused forward on gfx950's 16x16x32 BF16 MFMA.  Operand layout (lane l):
 //   A (16 x 32, rows i, k):  row l % 16, k = 8 (l / 16) + t, t = 0..7
 //   B (32 x 16, k, cols j):  col l % 16, k = 8 (l / 16) + t
 //   C (16 x 16):             col l % 16, rows 4 (l / 16) + t, t = 0..3
+// Each layer is computed transposed, Z^T = W^T H^T: A is a 16-feature slice
+// of W^T (eight contiguous k-values per lane: one 16-byte load), B a
+// 16-row slice of the activations (one 16-byte LDS read), and each lane's
+// four results are four consecutive features of one row, stored as one
+// 8-byte LDS write (16 bytes for FP32 outputs).
 // A block of 256 threads owns 64 rows; the activations of all five layers
 // stay in two 64 x 264 BF16 LDS buffers (67.6 KB: two blocks per CU).
-// Wave w owns the column tiles [w CTW, (w + 1) CTW) of a layer and all four
-// row tiles; each lane's eight k-values of a weight column are one 16-byte
-// load from W^T, issued one k-step ahead of the MFMAs that use them.
+// Wave w owns the feature tiles [w CTW, (w + 1) CTW) of a layer and all
+// four row tiles; weight fragments are loaded one k-step ahead.
 // ---------------------------------------------------------------------------
 constexpr int TM = 64;       // rows per block
 constexpr int RT = TM / 16;  // row tiles
@@ -92,13 +112,15 @@ struct FwdArgs {
     uint16_t* hsave[4];  // [n][256] BF16 activations (nullable)
 };
 
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
 // One layer: out[TM][NOUT] = act(in[TM][K] W + b).
 template <int K, int NOUT, bool LAST>
 __device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const uint16_t* in,
                                           uint16_t* out, int64_t row0)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    constexpr int CT = NOUT / 16;                 // column tiles
+    constexpr int CT = NOUT / 16;                 // feature tiles
     constexpr int CTW = (CT + 3) / 4;             // per wave
     constexpr int KS = K / 32;                    // k-steps
     const int c0 = w * CTW;
@@ -109,52 +131,50 @@ __device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const uin
         for (int c = 0; c < CTW; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint16_t* WT = a.WT[layer];
     const int kq = 8 * (lane >> 4), li = lane & 15;
-    s16x8 bnext[CTW];
+    s16x8 wnext[CTW];
 #pragma unroll
     for (int c = 0; c < CTW; ++c)
-        bnext[c] = (c0 + c < CT) ? *(const s16x8*)(WT + (int64_t)((c0 + c) * 16 + li) * K + kq)
+        wnext[c] = (c0 + c < CT) ? *(const s16x8*)(WT + (int64_t)((c0 + c) * 16 + li) * K + kq)
                                  : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int k0 = ks * 32;
-        s16x8 bf[CTW];
+        s16x8 wf[CTW];
 #pragma unroll
         for (int c = 0; c < CTW; ++c) {
-            bf[c] = bnext[c];
+            wf[c] = wnext[c];
             if (ks + 1 < KS && c0 + c < CT)
-                bnext[c] = *(const s16x8*)(WT + (int64_t)((c0 + c) * 16 + li) * K + k0 + 32 + kq);
+                wnext[c] = *(const s16x8*)(WT + (int64_t)((c0 + c) * 16 + li) * K + k0 + 32 + kq);
         }
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
-            const s16x8 af = *(const s16x8*)(in + (r * 16 + li) * LDH + k0 + kq);
+            const s16x8 hf = *(const s16x8*)(in + (r * 16 + li) * LDH + k0 + kq);
 #pragma unroll
-            for (int c = 0; c < CTW; ++c) acc[r][c] = mfma32(af, bf[c], acc[r][c]);
+            for (int c = 0; c < CTW; ++c) acc[r][c] = mfma32(wf[c], hf, acc[r][c]);
         }
     }
     const float* bias = a.b[layer];
-    const int rq = 4 * (lane >> 4);
+    const int fq = 4 * (lane >> 4);
 #pragma unroll
     for (int c = 0; c < CTW; ++c) {
         if (c0 + c >= CT) continue;
-        const int col = (c0 + c) * 16 + li;
-        const float bc = bias[col];
+        const int f = (c0 + c) * 16 + fq;      // first of this lane's four features
+        const f32x4 bc = *(const f32x4*)(bias + f);
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
+            const int row = r * 16 + li;
+            const int64_t grow = row0 + row;
+            const f32x4 z = acc[r][c] + bc;
+            if (LAST) {
+                if (grow < a.n) *(f32x4*)(a.Y + grow * 48 + f) = z;
+            } else {
+                u16x4 hb;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int row = r * 16 + rq + t;
-                const int64_t grow = row0 + row;
-                const float z = acc[r][c][t] + bc;
-                if (LAST) {
-                    if (grow < a.n) a.Y[grow * 48 + col] = z;
-                } else {
-                    const float h = gelu(z);
-                    const uint16_t hb = f2bf(h);
-                    out[row * LDH + col] = hb;
-                    if (grow < a.n) {
-                        if (a.zsave[layer]) a.zsave[layer][grow * 256 + col] = z;
-                        if (a.hsave[layer]) a.hsave[layer][grow * 256 + col] = hb;
-                    }
+                for (int t = 0; t < 4; ++t) hb[t] = f2bf(gelu_fast(z[t]));
+                *(u16x4*)(out + row * LDH + f) = hb;
+                if (grow < a.n) {
+                    if (a.zsave[layer]) *(f32x4*)(a.zsave[layer] + grow * 256 + f) = z;
+                    if (a.hsave[layer]) *(u16x4*)(a.hsave[layer] + grow * 256 + f) = hb;
                 }
             }
         }
