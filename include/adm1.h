@@ -324,8 +324,9 @@ int adm1_surrogate_get_weights(adm1_surrogate *s, float *params, adm1_mlp_norm *
  * [ADM1_MLP_PARAMS], same layout as the weights).  Synchronous. */
 int adm1_surrogate_get_grads(adm1_surrogate *s, float *grads);
 
-/* Network inputs of particles 0..n-1: X = BF16 [n][64] (uint16 bit patterns).
- * D: [n] dilution rates (the feed flag is D > 0). */
+/* Network inputs of particles 0..n-1: X = BF16 [n][64] (uint16 bit patterns,
+ * 16-byte aligned, else ADM1_E_SIZE).  D: [n] dilution rates (the feed flag
+ * is D > 0). */
 int adm1_surrogate_featurize(adm1_surrogate *s, const double *state, int64_t ld,
                              const double *temp_K, const double *D, double dt_days, int64_t n,
                              uint16_t *X, void *stream);

@@ -391,15 +391,26 @@ __global__ void __launch_bounds__(256) k_featurize(const double* state, int64_t 
     if (i >= n) return;
     const float* mean = norm;
     const float* sd = norm + 38;
-    uint16_t* xo = X + i * 64;
-    for (int k = 0; k < 35; ++k) {
-        const double v = fmax(state[k * ld + i], floor_[k]);
-        xo[k] = f2bf(((float)log(v) - mean[k]) / sd[k]);
+    // the row is assembled in registers and written as eight 16-byte stores
+    s16x8 row[8];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+        float v = 0.0f;
+        if (k < 35) {
+            const double x = fmax(state[k * ld + i], floor_[k]);
+            v = ((float)log(x) - mean[k]) / sd[k];
+        } else if (k == 35) {
+            v = ((float)T[i] - mean[35]) / sd[35];
+        } else if (k == 36) {
+            v = ((float)log(dt) - mean[36]) / sd[36];
+        } else if (k == 37) {
+            v = ((D[i] > 0.0 ? 1.f : 0.f) - mean[37]) / sd[37];
+        }
+        row[k >> 3][k & 7] = (short)(k < 38 ? f2bf(v) : 0);
     }
-    xo[35] = f2bf(((float)T[i] - mean[35]) / sd[35]);
-    xo[36] = f2bf(((float)log(dt) - mean[36]) / sd[36]);
-    xo[37] = f2bf(((D[i] > 0.0 ? 1.f : 0.f) - mean[37]) / sd[37]);
-    for (int k = 38; k < 64; ++k) xo[k] = 0;
+    s16x8* xo = (s16x8*)(X + i * 64);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xo[q] = row[q];
 }
 
 // Training targets: standardised increments of log(max(x, floor)).

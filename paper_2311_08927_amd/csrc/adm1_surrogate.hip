@@ -470,6 +470,7 @@ int adm1_surrogate_featurize(adm1_surrogate* s, const double* state, int64_t ld,
     if (rc) return rc;
     if (!state || !temp_K || !D || !X) return ADM1_E_NULL;
     if ((rc = check_layout(s->ctx, ld, n))) return rc;
+    if (((uintptr_t)X & 15) != 0) return ADM1_E_SIZE;
     if (!(dt_days > 0.0) || !std::isfinite(dt_days)) return ADM1_E_DT;
     if (!is_device(state) || !is_device(temp_K) || !is_device(D) || !is_device(X))
         return ADM1_E_NOT_DEVICE;
