@@ -108,6 +108,17 @@ __device__ __forceinline__ TConst load_tc(const Lds& L, int pr)
     return c;
 }
 
+// Rarely executed transcendental work (once per particle) kept out of line,
+// so that the constants of exp/log are not hoisted into the persistent loop.
+__device__ __attribute__((noinline)) TConst tconst_ool(const DevParams* p, double T)
+{
+    return tconst(*p, T);
+}
+__device__ __attribute__((noinline)) double fifth_root(double x)
+{
+    return exp(0.2 * log(x));
+}
+
 // Per-pair integration state kept in registers across loop iterations.
 struct PairState {
     double t, h, H, Sh2, hlast;
@@ -141,8 +152,11 @@ __device__ __forceinline__ void write_status(const StepArgs& a, const PairState&
 template <typename R>
 __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairState& s,
                                int& job, int fin_status, bool& active, bool& exhausted,
-                               bool odd, int lane, int64_t total)
+                               bool odd_in, int lane_in, int64_t total)
 {
+    int lane = lane_in;
+    asm volatile("" : "+v"(lane));
+    const bool odd = lane & 1;
     const int pr = lane >> 1;
     double yin[NY], f[NY], f0[NY];
     double h0 = 0.0, d1 = 0.0;
@@ -210,7 +224,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                 job = kNone;
                 run = false;
             } else {
-                c = tconst(p, T);
+                c = tconst_ool(&p, T);
                 if (!odd) {
                     L.tc[0][pr] = c.RT; L.tc[1][pr] = c.K_w; L.tc[2][pr] = c.K_a_co2;
                     L.tc[3][pr] = c.K_a_IN; L.tc[4][pr] = c.K_H_h2; L.tc[5][pr] = c.K_H_ch4;
@@ -306,7 +320,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                 d2 = sqrt(d2 / NY) / h0;
                 const double dm = fmax(d1, d2);
                 const double h1 =
-                    (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : exp(0.2 * log(0.01 / dm));
+                    (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : fifth_root(0.01 / dm);
                 h = fmin(fmin(100.0 * h0, h1), a.dt);
             }
             s.h = h;
@@ -337,8 +351,13 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
 // not unrolled: one right-hand-side, factorisation and solve site.
 template <typename R>
 __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState& s,
-                              bool odd, int lane)
+                              bool odd_in, int lane_in)
 {
+    // lane-dependent values (row selections, LDS offsets) are recomputed
+    // here rather than kept live across the persistent loop
+    int lane = lane_in;
+    asm volatile("" : "+v"(lane));
+    const bool odd = lane & 1;
     const int pr = lane >> 1;
     {
         const DevParams& p = params_at(pp);
