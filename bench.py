@@ -326,28 +326,42 @@ def surrogate_main(args):
     tot = {p: torch.zeros((K, 4), dtype=torch.float64, device=dev) for p in ("fp64", "sur")}
     fb = torch.zeros(K, dtype=torch.int32, device=dev)
     out_state, out_H, ms = {}, {}, {}
+    # one coupling step of each path captured as a HIP graph (step + gas
+    # flux); the feed mask writes D / fidx before each replay
+    cap = torch.cuda.Stream()
+    tot_g = torch.zeros(4, dtype=torch.float64, device=dev)
+    fb_g = torch.zeros(1, dtype=torch.int32, device=dev)
+    feed = A.feed_struct(D, fidx, S_in)
+    aux = A.adm1_aux(H.data_ptr(), hl.data_ptr())
+    graphs = {
+        "fp64": A.adm1_graph_capture_step(ctx.handle, X, wd.ld, T, feed, wd.dt, wd.n, aux,
+                                          status, None, V, None, None, tot_g, cap),
+        "sur": S.adm1_surrogate_graph_capture_step(sur.handle, X, wd.ld, T, feed, wd.dt, wd.n,
+                                                   gate, aux, status, None, None, fb_g, V,
+                                                   None, None, tot_g, cap),
+    }
+    stream = torch.cuda.current_stream()
     for path in ("fp64", "sur"):
         X.copy_(X0); H.copy_(H0); hl.copy_(hl0); pos.copy_(pos0)
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(K)]
         for k in range(K):
-            # timed: feed mask, the particle step, gas flux; the advection of
-            # the coupling driver is outside the metric
+            # timed: feed mask and the captured step + gas flux; the
+            # advection of the coupling driver is outside the metric
             ev[k][0].record()
             mask()
-            if path == "fp64":
-                ctx.step(X, T, D, fidx, S_in, wd.dt, n=wd.n, H=H, hlast=hl, status=status)
-            else:
-                sur.step(X, T, D, fidx, S_in, wd.dt, gate, n=wd.n, H=H, hlast=hl,
-                         status=status, fb_count=fb[k:k + 1])
-            A.adm1_gas_flux(ctx.handle, X, wd.ld, T, V, wd.n, None, None, tot[path][k])
+            A.adm1_graph_launch(graphs[path], stream)
             ev[k][1].record()
+            tot[path][k].copy_(tot_g)
+            fb[k:k + 1].copy_(fb_g)
             A.adm1_advect(pos, wd.ld, wd.n, flow, dt_s, int(dt_s))
             log(f"# {path} step {k} enqueued")
         torch.cuda.synchronize()
         ms[path] = sum(e0.elapsed_time(e1) for e0, e1 in ev)
         out_state[path], out_H[path] = X.clone(), H.clone()
+    for gph in graphs.values():
+        A.adm1_graph_destroy(gph)
     # forward kernel alone on the field's features (MFMA roofline)
     Xf = sur.featurize(X0, T, D, wd.dt, wd.n)
     sur.forward(Xf)
@@ -377,7 +391,8 @@ def surrogate_main(args):
         "config": {"workload": f"digester field: {wd.n} particles in the r 0.1 m, h 0.3 m "
                                f"cylinder, seeded flow, top-inlet pulse feed, 308.5 K, "
                                f"{K} coupling steps of 1/96 d after {args.burn_in} FP64 "
-                               f"burn-in steps", "path": "gated surrogate",
+                               f"burn-in steps, each path's step captured in a HIP graph",
+                   "path": "gated surrogate",
                    "gate": {"max_dlog": gate.max_dlog, "tol_ion": gate.tol_ion,
                             "tol_closure": gate.tol_closure}},
         "roofline": {"bound": "mfma", "achieved": mlp_flop / (fwd_ms / 1e3) / 1e12,

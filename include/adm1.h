@@ -363,6 +363,20 @@ int adm1_surrogate_step(adm1_surrogate *s, double *state, int64_t ld, const doub
                         const adm1_gate *gate, adm1_aux *aux, uint8_t *status,
                         int32_t *nsteps, uint8_t *route, int32_t *fb_count, void *stream);
 
+/* The gated surrogate step followed by adm1_gas_flux, captured as a HIP graph
+ * (launched and destroyed with adm1_graph_launch / adm1_graph_destroy).
+ * Arguments as in adm1_surrogate_step and adm1_gas_flux; the capture records
+ * kernel launches only (the fallback count is cleared by a kernel and read
+ * by the fallback kernel from device memory).  `stream` (a hipStream_t, not
+ * NULL) is used for capture and left idle.  Synchronous. */
+int adm1_surrogate_graph_capture_step(adm1_surrogate *s, double *state, int64_t ld,
+                                      const double *temp_K, const adm1_feed *feed,
+                                      double dt_days, int64_t n, const adm1_gate *gate,
+                                      adm1_aux *aux, uint8_t *status, int32_t *nsteps,
+                                      uint8_t *route, int32_t *fb_count, const double *V_liq,
+                                      double *q_gas, double *q_ch4, double *totals,
+                                      void *stream, adm1_graph **out);
+
 /* One training step on a batch of B rows: X BF16 [B][64], target float32
  * [B][35]; forward, mean-squared-error loss (written to *loss, device
  * float32, before the update), backward, Adam with learning rate lr at step

@@ -229,6 +229,23 @@ int check_feed(const adm1_feed* feed)
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? ADM1_OK : (int)e; }
 
+int finish_capture(hipStream_t s, int rc, adm1_graph* g, adm1_graph** out)
+{
+    hipError_t e = hipStreamEndCapture(s, &g->graph);
+    if (rc == ADM1_OK && e != hipSuccess) rc = (int)e;
+    if (rc == ADM1_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = (int)e;
+    }
+    if (rc != ADM1_OK) {
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return rc;
+    }
+    *out = g;
+    return ADM1_OK;
+}
+
 }  // namespace adm1_abi
 
 using namespace adm1_abi;
@@ -433,10 +450,6 @@ int adm1_set_launch(adm1_ctx* ctx, int32_t variant, int32_t blocks_per_cu)
     return ADM1_OK;
 }
 
-struct adm1_graph {
-    hipGraph_t graph;
-    hipGraphExec_t exec;
-};
 
 int adm1_graph_capture_step(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,
                             const adm1_feed* feed, double dt_days, int64_t n, adm1_aux* aux,
@@ -460,19 +473,7 @@ int adm1_graph_capture_step(adm1_ctx* ctx, double* state, int64_t ld, const doub
                                  nsteps, stream);
     if (rc == ADM1_OK)
         rc = adm1_gas_flux(ctx, state, ld, temp_K, V_liq, n, q_gas, q_ch4, totals, stream);
-    e = hipStreamEndCapture(s, &g->graph);
-    if (rc == ADM1_OK && e != hipSuccess) rc = (int)e;
-    if (rc == ADM1_OK) {
-        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) rc = (int)e;
-    }
-    if (rc != ADM1_OK) {
-        if (g->graph) (void)hipGraphDestroy(g->graph);
-        delete g;
-        return rc;
-    }
-    *out = g;
-    return ADM1_OK;
+    return finish_capture(s, rc, g, out);
 }
 
 int adm1_graph_launch(adm1_graph* g, void* stream)

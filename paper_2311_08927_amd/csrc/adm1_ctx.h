@@ -20,9 +20,18 @@ struct adm1_ctx {
     int tuned_blocks_per_cu;
 };
 
+// A captured coupling step (adm1_graph_capture_step and its surrogate
+// counterpart).
+struct adm1_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
 namespace adm1_abi {
 bool is_device(const void* ptr);
 int check_layout(const adm1_ctx* ctx, int64_t ld, int64_t n);
 int check_feed(const adm1_feed* feed);
 int hip_rc(hipError_t e);
+// End a capture begun on s, instantiate the graph into *g (freed on error).
+int finish_capture(hipStream_t s, int rc, adm1_graph* g, adm1_graph** out);
 }  // namespace adm1_abi

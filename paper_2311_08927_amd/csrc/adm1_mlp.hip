@@ -391,26 +391,29 @@ __global__ void __launch_bounds__(256) k_featurize(const double* state, int64_t 
     if (i >= n) return;
     const float* mean = norm;
     const float* sd = norm + 38;
-    // the row is assembled in registers and written as eight 16-byte stores
-    s16x8 row[8];
-#pragma unroll
-    for (int k = 0; k < 64; ++k) {
-        float v = 0.0f;
-        if (k < 35) {
-            const double x = fmax(state[k * ld + i], floor_[k]);
-            v = ((float)log(x) - mean[k]) / sd[k];
-        } else if (k == 35) {
-            v = ((float)T[i] - mean[35]) / sd[35];
-        } else if (k == 36) {
-            v = ((float)log(dt) - mean[36]) / sd[36];
-        } else if (k == 37) {
-            v = ((D[i] > 0.0 ? 1.f : 0.f) - mean[37]) / sd[37];
-        }
-        row[k >> 3][k & 7] = (short)(k < 38 ? f2bf(v) : 0);
-    }
+    // the row is written as eight 16-byte stores of eight features each
     s16x8* xo = (s16x8*)(X + i * 64);
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+        s16x8 v;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) xo[q] = row[q];
+        for (int t = 0; t < 8; ++t) {
+            const int k = q * 8 + t;
+            float f = 0.0f;
+            if (k < 35) {
+                const double x = fmax(state[k * ld + i], floor_[k]);
+                f = ((float)log(x) - mean[k]) / sd[k];
+            } else if (k == 35) {
+                f = ((float)T[i] - mean[35]) / sd[35];
+            } else if (k == 36) {
+                f = ((float)log(dt) - mean[36]) / sd[36];
+            } else if (k == 37) {
+                f = ((D[i] > 0.0 ? 1.f : 0.f) - mean[37]) / sd[37];
+            }
+            v[t] = (short)(k < 38 ? f2bf(f) : 0);
+        }
+        xo[q] = v;
+    }
 }
 
 // Training targets: standardised increments of log(max(x, floor)).

@@ -579,6 +579,42 @@ int adm1_surrogate_step(adm1_surrogate* s, double* state, int64_t ld, const doub
                                             st));
 }
 
+int adm1_surrogate_graph_capture_step(adm1_surrogate* s, double* state, int64_t ld,
+                                      const double* temp_K, const adm1_feed* feed,
+                                      double dt_days, int64_t n, const adm1_gate* gate,
+                                      adm1_aux* aux, uint8_t* status, int32_t* nsteps,
+                                      uint8_t* route, int32_t* fb_count, const double* V_liq,
+                                      double* q_gas, double* q_ch4, double* totals,
+                                      void* stream, adm1_graph** out)
+{
+    int rc = check_surrogate(s);
+    if (rc) return rc;
+    if (!out || !stream || !feed || !gate) return ADM1_E_NULL;
+    if (n < 0 || n > s->n_max) return ADM1_E_SIZE;
+    if (!(gate->max_dlog >= 0.0) || !(gate->tol_ion >= 0.0) || !(gate->tol_closure >= 0.0))
+        return ADM1_E_OPTS;
+    // validate the step's arguments before capturing (n = 0 enqueues nothing)
+    if ((rc = adm1_step_particles(s->ctx, state, ld, temp_K, feed, dt_days, 0, aux, status,
+                                  nsteps, stream)))
+        return rc;
+    if (!totals) return ADM1_E_NULL;
+    adm1_graph* g = new (std::nothrow) adm1_graph;
+    if (!g) return ADM1_E_NOMEM;
+    g->graph = nullptr;
+    g->exec = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    const hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        delete g;
+        return (int)e;
+    }
+    rc = adm1_surrogate_step(s, state, ld, temp_K, feed, dt_days, n, gate, aux, status, nsteps,
+                             route, fb_count, stream);
+    if (rc == ADM1_OK)
+        rc = adm1_gas_flux(s->ctx, state, ld, temp_K, V_liq, n, q_gas, q_ch4, totals, stream);
+    return finish_capture(st, rc, g, out);
+}
+
 int adm1_surrogate_train_step(adm1_surrogate* s, const uint16_t* X, const float* target,
                               int64_t B, float lr, int32_t step, float* loss, void* stream)
 {

@@ -54,6 +54,9 @@ def _lib():
                                     vp, vp],
             "adm1_surrogate_step": [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, vp],
             "adm1_surrogate_train_step": [vp, vp, vp, i64, flt, i32, vp, vp],
+            "adm1_surrogate_graph_capture_step": [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp,
+                                                  vp, vp, vp, vp, vp, vp, vp, vp,
+                                                  ctypes.POINTER(vp)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -163,6 +166,20 @@ def adm1_surrogate_step(s, state, ld, temp_K, feed, dt_days, n, gate: adm1_gate,
         s, _p(state), int(ld), _p(temp_K), ctypes.byref(feed), float(dt_days), int(n),
         ctypes.byref(gate), None if aux is None else ctypes.byref(aux), _p(status),
         _p(nsteps), _p(route), _p(fb_count), _s(stream)), "adm1_surrogate_step")
+
+
+def adm1_surrogate_graph_capture_step(s, state, ld, temp_K, feed, dt_days, n, gate: adm1_gate,
+                                      aux, status, nsteps, route, fb_count, V_liq, q_gas,
+                                      q_ch4, totals, stream) -> int:
+    """Capture the gated step + gas flux as a graph (launch/destroy with
+    adm1.adm1_graph_launch / adm1.adm1_graph_destroy)."""
+    g = ctypes.c_void_p()
+    _check(_lib().adm1_surrogate_graph_capture_step(
+        s, _p(state), int(ld), _p(temp_K), ctypes.byref(feed), float(dt_days), int(n),
+        ctypes.byref(gate), None if aux is None else ctypes.byref(aux), _p(status), _p(nsteps),
+        _p(route), _p(fb_count), _p(V_liq), _p(q_gas), _p(q_ch4), _p(totals), _s(stream),
+        ctypes.byref(g)), "adm1_surrogate_graph_capture_step")
+    return g.value
 
 
 def adm1_surrogate_train_step(s, X, target, B, lr, step, loss, stream=None):

@@ -275,6 +275,56 @@ def test_zero_gate_is_bit_identical_to_the_integrator(torch_cuda):
             assert torch.equal(t1, t2)
 
 
+def test_graph_replay_matches_eager(torch_cuda):
+    """Replays of the captured gated step (+ gas flux) equal the eager calls
+    bit for bit over three coupling intervals, with a gate that accepts some
+    proposals and rejects others (so the fallback list varies)."""
+    torch = torch_cuda
+    from paper_2311_08927_amd import adm1 as A
+    from paper_2311_08927_amd import surrogate as S
+    full = W.batched_population(1 << 12, seed=2)
+    w = W.subset(full, np.arange(0, full.n, 4))
+    ctx, sur = make(w.ld)
+    sur.set_weights(seeded_params(3), seeded_norm(3))
+    gate = S.adm1_gate(5.0, 0.5, 0.05)
+    e, g = DeviceWorkload(w), DeviceWorkload(w)
+    V = torch.full((w.n,), 1.0, dtype=torch.float64, device="cuda")
+    out = {k: (torch.empty(w.n, dtype=torch.float64, device="cuda"),
+               torch.empty(w.n, dtype=torch.float64, device="cuda"),
+               torch.empty(4, dtype=torch.float64, device="cuda"),
+               torch.zeros(1, dtype=torch.int32, device="cuda"),
+               torch.empty(w.n, dtype=torch.uint8, device="cuda")) for k in "eg"}
+    s = torch.cuda.Stream()
+    qg, qc, tot, fb, route = out["g"]
+    graph = S.adm1_surrogate_graph_capture_step(
+        sur.handle, g.X, w.ld, g.T, A.feed_struct(g.D, g.fidx, g.S_in), w.dt, w.n, gate,
+        A.adm1_aux(g.H.data_ptr(), g.hlast.data_ptr()), g.status, g.nsteps, route, fb, V, qg,
+        qc, tot, s)
+    try:
+        counts = []
+        for k in range(3):
+            D = torch.from_numpy(w.D_at(k)).cuda()
+            e.D.copy_(D)
+            g.D.copy_(D)
+            torch.cuda.synchronize()
+            qe, qce, tote, fbe, routee = out["e"]
+            sur.step(e.X, e.T, e.D, e.fidx, e.S_in, w.dt, gate, n=w.n, H=e.H, hlast=e.hlast,
+                     status=e.status, nsteps=e.nsteps, route=routee, fb_count=fbe)
+            A.adm1_gas_flux(ctx.handle, e.X, w.ld, e.T, V, w.n, qe, qce, tote)
+            A.adm1_graph_launch(graph, s)
+            s.synchronize()
+            torch.cuda.synchronize()
+            counts.append(int(fbe.item()))
+            for t1, t2 in ((e.X, g.X), (e.H, g.H), (e.hlast, g.hlast), (e.status, g.status),
+                           (e.nsteps, g.nsteps), (routee, route), (fbe, fb), (qe, qg),
+                           (tote, tot)):
+                assert torch.equal(t1, t2)
+        print("fallback counts per replay:", counts, "of", w.n)
+        assert any(0 < c < w.n for c in counts)
+    finally:
+        A.adm1_graph_destroy(graph)
+
+
 def test_trained_network_beats_untrained(torch_cuda):
     """Train on integrator transitions (own forward/backward/Adam kernels);
     on held-out particles the trained network's error is far below the
