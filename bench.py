@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--burn-in", type=int, default=2,
                     help="surrogate path: untimed FP64 steps before the comparison")
     ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--rate-precision", type=int, default=0, choices=[0, 1],
+                    help="1: rates and eq. 2 assembly in FP32 (the FP32-rate experiment)")
     ap.add_argument("--blocks-per-cu", type=int, default=0,
                     help="resident waves per CU of the persistent step kernel (0: library "
                          "default)")
@@ -134,7 +136,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     w = W.batched_population(args.n, seed=2, steps=args.steps)
-    ctx = A.Context(w.ld, rtol=args.rtol, atol=W.atol_vector(args.rtol), variant=args.variant)
+    ctx = A.Context(w.ld, rtol=args.rtol, atol=W.atol_vector(args.rtol), variant=args.variant,
+                    rate_precision=args.rate_precision)
     if args.blocks_per_cu > 0:
         A.adm1_set_launch(ctx.handle, A.VARIANT_SPARSE2, args.blocks_per_cu)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
@@ -209,7 +212,8 @@ def main():
     achieved = flop / kern_s
     value = w.n * K / (total_ms / 1e3)
     traffic = None
-    if args.n == 1 << 20 and K == 10 and args.rtol == 1e-8 and args.variant in (-1, 2):
+    if (args.n == 1 << 20 and K == 10 and args.rtol == 1e-8 and args.variant in (-1, 2) and
+            args.rate_precision == 0):
         traffic = measured_traffic()
     out = {
         "metric": "ADM1 particle-steps/sec (FP64 integrator vs gated surrogate) at stated error",
@@ -222,13 +226,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.rate_precision == 0 else "f64 (rates f32)",
         "data": "synthetic",
         "config": {"workload": "batched ADM1 population: 2^20 particles, T U(30,40) C, 5% "
                                "pulsed feed zone, 10 coupling steps of 1/96 d, rtol 1e-8"
                    if args.n == 1 << 20 else f"batched ADM1 population, n={args.n}",
                    "particles": w.n, "coupling_steps": K, "dt_days": w.dt, "rtol": args.rtol,
-                   "path": "fp64 integrator", "variant": args.variant},
+                   "path": "fp64 integrator" if args.rate_precision == 0 else
+                   "fp64 integrator, fp32 rates", "variant": args.variant},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic,
                      "kernel": "adm1 step (k_step*)",
@@ -331,13 +336,20 @@ def surrogate_main(args):
     cap = torch.cuda.Stream()
     tot_g = torch.zeros(4, dtype=torch.float64, device=dev)
     fb_g = torch.zeros(1, dtype=torch.int32, device=dev)
+    route_g = torch.zeros(wd.n, dtype=torch.uint8, device=dev)
+    # audit sample: 4,096 seeded particles integrated exactly from their
+    # pre-step states after each surrogate step (outside the timed region)
+    aud = torch.from_numpy(np.sort(np.random.default_rng(7).choice(wd.n, 4096, replace=False)))
+    aud = aud.to(dev)
+    nom = torch.from_numpy(W.nominal()["state"]).to(dev)[:, None]
+    audit_max, audit_p99, audit_n = [], [], []
     feed = A.feed_struct(D, fidx, S_in)
     aux = A.adm1_aux(H.data_ptr(), hl.data_ptr())
     graphs = {
         "fp64": A.adm1_graph_capture_step(ctx.handle, X, wd.ld, T, feed, wd.dt, wd.n, aux,
                                           status, None, V, None, None, tot_g, cap),
         "sur": S.adm1_surrogate_graph_capture_step(sur.handle, X, wd.ld, T, feed, wd.dt, wd.n,
-                                                   gate, aux, status, None, None, fb_g, V,
+                                                   gate, aux, status, None, route_g, fb_g, V,
                                                    None, None, tot_g, cap),
     }
     stream = torch.cuda.current_stream()
@@ -351,8 +363,21 @@ def surrogate_main(args):
             # advection of the coupling driver is outside the metric
             ev[k][0].record()
             mask()
+            if path == "sur":
+                pre = (X.index_select(1, aud), H.index_select(0, aud), hl.index_select(0, aud),
+                       D.index_select(0, aud), fidx.index_select(0, aud))
             A.adm1_graph_launch(graphs[path], stream)
             ev[k][1].record()
+            if path == "sur":
+                Xa, Ha, hla, Da, fia = pre
+                ctx.step(Xa, T.index_select(0, aud), Da, fia, S_in, wd.dt, n=aud.numel(),
+                         H=Ha, hlast=hla)
+                acc = route_g.index_select(0, aud).bool()
+                err = ((X.index_select(1, aud) - Xa).abs() /
+                       torch.maximum(Xa.abs(), 1e-4 * nom)).amax(dim=0)[acc]
+                audit_n.append(int(acc.sum()))
+                audit_max.append(float(err.max()) if err.numel() else 0.0)
+                audit_p99.append(float(torch.quantile(err.float(), 0.99)) if err.numel() else 0.0)
             tot[path][k].copy_(tot_g)
             fb[k:k + 1].copy_(fb_g)
             A.adm1_advect(pos, wd.ld, wd.n, flow, dt_s, int(dt_s))
@@ -404,6 +429,10 @@ def surrogate_main(args):
                    "fallback_fraction": (fb.cpu().numpy() / wd.n).tolist(),
                    "tank_methane_rel_err": ch4_err,
                    "ph_rel_err_max": float(eph.max()),
+                   "audit": {"sample": "4096 seeded particles per step; accepted ones "
+                                       "integrated exactly from their pre-step states",
+                             "accepted": audit_n, "rel_err_max": audit_max,
+                             "rel_err_p99": audit_p99},
                    "ph_rel_err_p99": float(torch.quantile(eph[::max(1, wd.n >> 22)], 0.99)),
                    "train": {"transitions": int(keep.sum()), "epochs": args.train_epochs,
                              "steps": n_train_steps, "seconds": train_s,
