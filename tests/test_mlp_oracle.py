@@ -141,3 +141,25 @@ def test_gate_accepts_exact_transition_and_rejects_a_wrong_one(orc):
         # all-zero thresholds reject even the exact transition
         assert not M.gate(orc, values, x0, w.T[i], w.D[i], s_in, dt, delta, floor, -1.0,
                           0.0, 0.0, 0.0)[0]
+
+
+def test_features_and_targets_invert_their_definition():
+    """A state at exp(mean) standardises to zero features; a transition
+    x1 = max(x0, floor) exp(mean + sd z) has targets z."""
+    rng = np.random.default_rng(8)
+    floor = 1e-6 * W.nominal()["state"]
+    norm = {"in_mean": np.concatenate([np.log(W.nominal()["state"]) + 0.1 * rng.standard_normal(35),
+                                       [308.0, math.log(1 / 96), 1.0]]),
+            "in_sd": 0.5 + rng.random(38),
+            "out_mean": 0.01 * rng.standard_normal(35),
+            "out_sd": 0.05 + 0.1 * rng.random(35),
+            "floor": floor}
+    x = np.exp(norm["in_mean"][:35])[:, None]
+    f = M.features(x, np.array([308.0]), np.array([1.0]), 1 / 96, norm)
+    assert np.max(np.abs(f)) < 1e-5
+    z = rng.standard_normal((35, 5))
+    x0 = np.exp(norm["in_mean"][:35])[:, None] * np.exp(0.3 * rng.standard_normal((35, 5)))
+    x1 = np.maximum(x0, floor[:, None]) * np.exp(norm["out_mean"][:, None] +
+                                                norm["out_sd"][:, None] * z)
+    t = M.targets(x0, x1, norm)
+    assert np.max(np.abs(t - z.T)) < 1e-4
