@@ -69,7 +69,11 @@ def parse():
     ap.add_argument("--n", type=int, default=None,
                     help="particles (default 2^20 for the FP64 path, 2^24 for the surrogate)")
     ap.add_argument("--path", choices=["fp64", "surrogate"], default="fp64")
-    ap.add_argument("--train-epochs", type=int, default=8)
+    ap.add_argument("--train-epochs", type=int, default=24)
+    ap.add_argument("--gate-ion", type=float, default=1e-2,
+                    help="surrogate gate: tolerance of the proposed ions and S_h2")
+    ap.add_argument("--gate-closure", type=float, default=1e-3,
+                    help="surrogate gate: tolerance of the COD / nitrogen closure")
     ap.add_argument("--burn-in", type=int, default=2,
                     help="surrogate path: untimed FP64 steps before the comparison")
     ap.add_argument("--variant", type=int, default=-1)
@@ -326,7 +330,7 @@ def surrogate_main(args):
         A.adm1_advect(pos, wd.ld, wd.n, flow, dt_s, int(dt_s))
     torch.cuda.synchronize()
     X0, H0, hl0, pos0 = X.clone(), H.clone(), hl.clone(), pos.clone()
-    gate = S.adm1_gate(5.0, 3e-2, 3e-3)
+    gate = S.adm1_gate(5.0, args.gate_ion, args.gate_closure)
     K = args.steps
     tot = {p: torch.zeros((K, 4), dtype=torch.float64, device=dev) for p in ("fp64", "sur")}
     fb = torch.zeros(K, dtype=torch.int32, device=dev)
