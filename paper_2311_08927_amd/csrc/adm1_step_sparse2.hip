@@ -119,6 +119,37 @@ __device__ __attribute__((noinline)) double fifth_root(double x)
     return exp(0.2 * log(x));
 }
 
+// Inflow terms D S_in seen by one lane's right-hand side: only the lane's
+// own rows are assembled (the partner's are discarded), so only those and the
+// S_h2 inflow of eq. 8 are loaded; the accessor takes a state row.
+struct PairInflow {
+    double own[NDP];
+    double sh2;
+    bool odd;
+    __device__ __forceinline__ double operator()(int row) const
+    {
+        if (row == ROW_SH2) return sh2;
+        const int k = row < ROW_SH2 ? row : row - 1;   // integration index
+        return ((kVarSide[k] != 0) == odd) ? own[kVarPair[k]] : 0.0;
+    }
+};
+
+__device__ __forceinline__ PairInflow pair_inflow(const double* sin, double D, bool odd)
+{
+    PairInflow f;
+    f.odd = odd;
+#pragma unroll
+    for (int m = 0; m < NDP; ++m) {
+        const int k0 = kVar0[m], k1 = kVar1[m];
+        const int r0 = k0 <= San ? state_row(k0) : -1;
+        const int r1 = k1 <= San ? state_row(k1) : -1;
+        const int r = odd ? r1 : r0;
+        f.own[m] = r >= 0 ? D * sin[r >= 0 ? r : 0] : 0.0;
+    }
+    f.sh2 = D * sin[ROW_SH2];
+    return f;
+}
+
 // Per-pair integration state kept in registers across loop iterations.
 struct PairState {
     double t, h, H, Sh2, hlast;
@@ -411,8 +442,8 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
             const DevParams& p = params_at(pp);
             const TConst c = load_tc(L, pr);
             const double D = L.tc[9][pr];
-            ok = rhs_in<R>(p, c, arg, D, FeedInflow{D, a.S_in + (int64_t)s.fi * NLIQ}, s.H,
-                           s.Sh2,
+            ok = rhs_in<R>(p, c, arg, D, pair_inflow(a.S_in + (int64_t)s.fi * NLIQ, D, odd),
+                           s.H, s.Sh2,
                            [&bv, odd](int k, double v) {
                                const int m = kVarPair[k];
                                if ((kVarSide[k] != 0) == odd) bv[m] = v;
