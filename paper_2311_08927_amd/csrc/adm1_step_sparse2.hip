@@ -262,6 +262,20 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                     L.tc[6][pr] = c.K_H_co2; L.tc[7][pr] = c.p_h2o; L.tc[8][pr] = c.arr;
                     L.tc[9][pr] = D;
                 }
+                if (s.hlast > 0.0 && s.H > 0.0) {
+                    // warm start: the input's algebraic entries and S_H+ are
+                    // the previous interval's solution at this state, and the
+                    // first stage solves eqs. 7-8 from them; no separate
+                    // evaluation at y0 is needed (a failure there is reported
+                    // as at the interval start)
+#pragma unroll
+                    for (int m = 0; m < NDP; ++m)
+                        s.y[m] = odd ? yin[kVar1[m]] : yin[kVar0[m]];
+                    s.h = fmin(a.dt, s.hlast);
+                    active = true;
+                    job = kNone;
+                    run = false;
+                }
             }
         } else {  // kHinit: second evaluation of the starting-step estimate
 #pragma unroll
@@ -449,6 +463,8 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
                                if ((kVarSide[k] != 0) == odd) bv[m] = v;
                            },
                            s.it) == 0;
+            // the first stage of the first attempt is the interval start
+            if (!ok && st == 0 && s.n == 0) return 1 + 1;
             if (st == 0) {
                 H0 = s.H;
                 S0 = s.Sh2;
