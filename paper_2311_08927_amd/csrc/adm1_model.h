@@ -213,11 +213,12 @@ __device__ __forceinline__ int rhs(const DevParams& p, const TConst& c, const do
                                    double* f, int& iters);
 
 // Right-hand side with the inflow terms D S_in supplied by `inflow` (one
-// accessor per storage layout of the feed).
+// accessor per storage layout of the feed).  With alg_only the evaluation
+// stops once S_H+ and S_h2 are solved (nothing is written to `out`).
 template <typename R, typename Y, typename Inflow, typename Out>
 __device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const Y& y,
                                       double D, const Inflow& inflow, double& H, double& Sh2,
-                                      const Out& out, int& iters)
+                                      const Out& out, int& iters, bool alg_only = false)
 {
     if (solve_H(p, c, y, H, iters)) return 1;
     const R a = (R)c.arr;
@@ -269,6 +270,7 @@ __device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const
     t.c12 = (double)b12;
     t.kh = c.K_H_h2 * c.RT * y[Gh2];
     if (solve_Sh2(p, t, D, Sh2, iters)) return 1;
+    if (alg_only) return 0;
     const R S = (R)Sh2;
     rho[6] = b7 * (R)p.K_I_h2_fa * frcp((R)p.K_I_h2_fa + S);
     const R ic4 = (R)p.K_I_h2_c4 * frcp((R)p.K_I_h2_c4 + S);

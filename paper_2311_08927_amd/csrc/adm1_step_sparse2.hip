@@ -285,9 +285,10 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
         }
         if (!run) continue;
         double Ht = s.H, St = s.Sh2;
+        // the end of the interval needs only the algebraic entries
         const int rc = rhs_in<R>(p, c, yin, D, FeedInflow{D, a.S_in + (int64_t)s.fi * NLIQ},
                                  Ht, St,
-                                 [&f](int k, double v) { f[k] = v; }, s.it);
+                                 [&f](int k, double v) { f[k] = v; }, s.it, job == kFinish);
         if (job == kFinish) {
             int st = 0;
             if (rc) {
