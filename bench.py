@@ -82,6 +82,9 @@ def parse():
     ap.add_argument("--blocks-per-cu", type=int, default=0,
                     help="resident waves per CU of the persistent step kernel (0: library "
                          "default)")
+    ap.add_argument("--order", choices=["cost", "index"], default="cost",
+                    help="work-queue order of the step kernel (cost: expected step count "
+                         "from the previous interval, largest first)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--cpu-sample", type=int, default=16384,
                     help="particles of the oracle CPU-baseline sample (0: skip)")
@@ -144,6 +147,7 @@ def main():
                     rate_precision=args.rate_precision)
     if args.blocks_per_cu > 0:
         A.adm1_set_launch(ctx.handle, A.VARIANT_SPARSE2, args.blocks_per_cu)
+    A.adm1_set_order(ctx.handle, A.ORDER_COST if args.order == "cost" else A.ORDER_INDEX)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     X0 = t(w.X)
     X = X0.clone()
@@ -237,7 +241,8 @@ def main():
                    if args.n == 1 << 20 else f"batched ADM1 population, n={args.n}",
                    "particles": w.n, "coupling_steps": K, "dt_days": w.dt, "rtol": args.rtol,
                    "path": "fp64 integrator" if args.rate_precision == 0 else
-                   "fp64 integrator, fp32 rates", "variant": args.variant},
+                   "fp64 integrator, fp32 rates", "variant": args.variant,
+                   "queue_order": args.order},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic,
                      "kernel": "adm1 step (k_step*)",

@@ -205,6 +205,31 @@ int adm1_jacobian(adm1_ctx *ctx, const double *state, int64_t ld, const double *
  * Set by the autotuner after timing the candidates.  Synchronous. */
 int adm1_set_launch(adm1_ctx *ctx, int32_t variant, int32_t blocks_per_cu);
 
+/* Order in which the persistent step kernel (ADM1_VARIANT_SPARSE2) takes
+ * particles from its work queue.  The particles are independent (sec. 4.3,
+ * where they are split into equal static chunks per thread) but their costs
+ * differ several-fold, so the tail of an index-ordered queue leaves a few
+ * expensive particles running on otherwise idle waves.
+ *   ADM1_ORDER_INDEX: 0..n-1.
+ *   ADM1_ORDER_COST (default): the permutation of adm1_cost_order on
+ *     aux->h_last, i.e. expected step count dt / h_last, largest first, cold
+ *     particles first of all.  Used when aux and aux->h_last are given.
+ * A particle's result does not depend on the order.  Returns ADM1_E_OPTS for
+ * another mode.  Synchronous (no device work). */
+enum { ADM1_ORDER_INDEX = 0, ADM1_ORDER_COST = 1 };
+int adm1_set_order(adm1_ctx *ctx, int32_t mode);
+
+/* The permutation behind ADM1_ORDER_COST: order[0..n-1] (int32, device) lists
+ * the particles 0..n-1 by non-increasing bucket
+ *   b_i = min(floor(8 dt_days / h_last[i]), 1023),  b_i = 1023 where
+ *   h_last[i] <= 0 or is NaN (cold start: no prediction),
+ * ties in an unspecified order (a counting sort).  h_last: [n] device.
+ * Uses the context's histogram scratch: calls on one context must not
+ * overlap (the step kernel's work queue has the same restriction).
+ * Asynchronous on `stream`; n <= 2^31 - 1. */
+int adm1_cost_order(adm1_ctx *ctx, const double *h_last, double dt_days, int64_t n,
+                    int32_t *order, void *stream);
+
 /* A coupling step captured as a HIP graph: adm1_step_particles followed by
  * adm1_gas_flux with fixed arguments (sec. 2.3: one synchronised coupling
  * interval).  Capture records kernel launches only (no memset nodes);

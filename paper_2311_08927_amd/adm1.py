@@ -74,6 +74,10 @@ def lib():
         L.adm1_jacobian.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, vp]
         L.adm1_set_launch.restype = ctypes.c_int
         L.adm1_set_launch.argtypes = [vp, i32, i32]
+        L.adm1_set_order.restype = ctypes.c_int
+        L.adm1_set_order.argtypes = [vp, i32]
+        L.adm1_cost_order.restype = ctypes.c_int
+        L.adm1_cost_order.argtypes = [vp, vp, dbl, i64, vp, vp]
         L.adm1_graph_capture_step.restype = ctypes.c_int
         L.adm1_graph_capture_step.argtypes = [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp,
                                               vp, vp, vp, vp, ctypes.POINTER(vp)]
@@ -231,6 +235,18 @@ def adm1_feed_mask(pos, ld, n, z_min, r_max, D_zone, fidx_zone, fidx_out, D, fid
 
 def adm1_set_launch(ctx: int, variant: int, blocks_per_cu: int = 0):
     _check(lib().adm1_set_launch(ctx, int(variant), int(blocks_per_cu)), "adm1_set_launch")
+
+
+ORDER_INDEX, ORDER_COST = 0, 1
+
+
+def adm1_set_order(ctx: int, mode: int):
+    _check(lib().adm1_set_order(ctx, int(mode)), "adm1_set_order")
+
+
+def adm1_cost_order(ctx: int, h_last, dt_days, n, order, stream=None):
+    _check(lib().adm1_cost_order(ctx, _ptr(h_last), float(dt_days), int(n), _ptr(order),
+                                 _stream(stream)), "adm1_cost_order")
 
 
 def adm1_graph_capture_step(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, n, aux, status,

@@ -288,6 +288,8 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
     c->n_max = n_max;
     c->tuned_variant = -1;
     c->tuned_blocks_per_cu = 0;
+    c->order_mode = ADM1_ORDER_COST;
+    const size_t order_work = (2 * adm1::kOrderBuckets + 1) * sizeof(int32_t);
     if (hipGetDevice(&c->device) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
@@ -298,11 +300,17 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
         hipMalloc(&c->d_params, sizeof(DevParams)) != hipSuccess ||
         hipMemcpy(c->d_params, &c->dp, sizeof(DevParams), hipMemcpyHostToDevice) !=
             hipSuccess ||
-        hipMemset(c->d_queue, 0, 64 * sizeof(int32_t)) != hipSuccess) {
+        hipMemset(c->d_queue, 0, 64 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->d_order, (size_t)(n_max > 0 ? n_max : 1) * sizeof(int32_t)) !=
+            hipSuccess ||
+        hipMalloc(&c->d_order_work, order_work) != hipSuccess ||
+        hipMemset(c->d_order_work, 0, order_work) != hipSuccess) {
         (void)hipGetLastError();
         if (c->d_queue) (void)hipFree(c->d_queue);
         if (c->d_partial) (void)hipFree(c->d_partial);
         if (c->d_params) (void)hipFree(c->d_params);
+        if (c->d_order) (void)hipFree(c->d_order);
+        if (c->d_order_work) (void)hipFree(c->d_order_work);
         delete c;
         return ADM1_E_NOMEM;
     }
@@ -329,6 +337,8 @@ void adm1_destroy(adm1_ctx* ctx)
     (void)hipFree(ctx->d_queue);
     (void)hipFree(ctx->d_partial);
     (void)hipFree(ctx->d_params);
+    (void)hipFree(ctx->d_order);
+    (void)hipFree(ctx->d_order_work);
     delete ctx;
 }
 
@@ -367,11 +377,40 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
     case ADM1_VARIANT_SPARSE1:
         return hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, true, s));
     case ADM1_VARIANT_SPARSE2:
+        // expensive particles first (predicted by the previous interval's
+        // last step size) so that the queue's tail is made of cheap ones
+        if (ctx->order_mode == ADM1_ORDER_COST && a.hlast && n <= INT32_MAX) {
+            rc = hip_rc(adm1::launch_cost_order(a.hlast, n, dt_days, ctx->d_order_work,
+                                                ctx->d_order, s));
+            if (rc) return rc;
+            a.index = ctx->d_order;
+            a.index_count = ctx->d_order_work + 2 * adm1::kOrderBuckets;
+            a.index_bound = n;
+        }
         return hip_rc(adm1::launch_step_sparse2(a, ctx->opts.rate_precision,
                                                 ctx->tuned_blocks_per_cu, s));
     default:
         return ADM1_E_VARIANT;
     }
+}
+
+int adm1_set_order(adm1_ctx* ctx, int32_t mode)
+{
+    if (!ctx) return ADM1_E_NULL;
+    if (mode != ADM1_ORDER_INDEX && mode != ADM1_ORDER_COST) return ADM1_E_OPTS;
+    ctx->order_mode = mode;
+    return ADM1_OK;
+}
+
+int adm1_cost_order(adm1_ctx* ctx, const double* h_last, double dt_days, int64_t n,
+                    int32_t* order, void* stream)
+{
+    if (!ctx || !h_last || !order) return ADM1_E_NULL;
+    if (n < 0 || n > INT32_MAX) return ADM1_E_SIZE;
+    if (!(dt_days > 0.0) || !std::isfinite(dt_days)) return ADM1_E_DT;
+    if (!is_device(h_last) || !is_device(order)) return ADM1_E_NOT_DEVICE;
+    return hip_rc(adm1::launch_cost_order(h_last, n, dt_days, ctx->d_order_work, order,
+                                          (hipStream_t)stream));
 }
 
 int adm1_gas_flux(adm1_ctx* ctx, const double* state, int64_t ld, const double* temp_K,

@@ -24,6 +24,7 @@ struct StepArgs {
     int32_t* queue;         // work-queue counter (persistent kernels)
     const int32_t* index;   // optional particle index list (nullable: identity)
     const int32_t* index_count;  // device count of the index list (with index)
+    int64_t index_bound;    // host upper bound of that count (0: unknown)
     const DevParams* pdev;  // device copy of p (read through the scalar cache)
 };
 
@@ -56,6 +57,15 @@ struct GasArgs {
 hipError_t launch_step1(const StepArgs& a, int rate_precision, bool sparse, hipStream_t s);
 hipError_t launch_step_sparse2(const StepArgs& a, int rate_precision, int blocks_per_cu,
                                hipStream_t s);
+// Cost order of the work queue: order[0..n-1] = particles by non-increasing
+// bucket min(floor(kOrderRes dt / hlast[i]), kOrderBuckets-1) (the last
+// bucket also for hlast[i] <= 0 or NaN).  work: int32 [2 kOrderBuckets + 1],
+// zero in its first kOrderBuckets entries before the first call (left so);
+// work[2 kOrderBuckets] receives n, the list length read by the queue.
+constexpr int kOrderBuckets = 1024;
+constexpr double kOrderRes = 8.0;
+hipError_t launch_cost_order(const double* hlast, int64_t n, double dt, int32_t* work,
+                             int32_t* order, hipStream_t s);
 hipError_t launch_rhs(const RhsArgs& a, int rate_precision, hipStream_t s);
 hipError_t launch_jacobian(const RhsArgs& a, double* J, hipStream_t s);
 hipError_t launch_gasflux(const GasArgs& a, int nblocks, double* totals, hipStream_t s);

@@ -614,8 +614,9 @@ hipError_t launch_step_sparse2(const StepArgs& a, int rate_precision, int blocks
     if (e != hipSuccess) return e;
     const int per_cu = blocks_per_cu > 0 ? blocks_per_cu : kWavesPerCU;
     int64_t grid = (int64_t)ncu * per_cu;
-    const int64_t need = (a.n + 31) / 32;
-    if (!a.index && need < grid) grid = need;
+    const int64_t bound = a.index ? a.index_bound : a.n;
+    const int64_t need = (bound + 31) / 32;
+    if ((!a.index || bound > 0) && need < grid) grid = need;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, a.queue);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -116,3 +116,68 @@ def test_sparse2_grid_sizes(torch_cuda, blocks):
     d1 = DeviceWorkload(w)
     ctx.step(d1.X, d1.T, d1.D, d1.fidx, d1.S_in, w.dt, n=w.n)
     assert np.array_equal(d0.X.cpu().numpy(), d1.X.cpu().numpy())
+
+
+def _cost_bucket(h: np.ndarray, dt: float) -> np.ndarray:
+    """Bucket of the cost order as its header comment defines it."""
+    b = np.full(h.shape, 1023, dtype=np.int64)
+    warm = h > 0.0
+    with np.errstate(divide="ignore", over="ignore"):
+        x = dt / h[warm] * 8.0
+    b[warm] = np.where(x < 1023.0, np.floor(np.minimum(x, 1023.0)), 1023).astype(np.int64)
+    return b
+
+
+@pytest.mark.parametrize("n", [1, 1000, (1 << 20) + 7])
+def test_cost_order_is_sorted_permutation(torch_cuda, n):
+    """adm1_cost_order returns a permutation of 0..n-1 along which the cost
+    bucket does not increase, for step sizes that span every bucket and the
+    special values (cold, zero, NaN, inf, denormal-sized); a second call on
+    the same context (smaller n) is right too (the histogram is left clear)."""
+    torch = torch_cuda
+    from paper_2311_08927_amd import adm1 as A
+    dt = W.DT
+    ctx = make_ctx(8)
+    g = np.random.default_rng(n)
+    for m in (n, max(1, n // 3)):
+        h = dt / np.exp(g.uniform(-2.0, 7.5, m))
+        special = g.integers(0, m, size=min(m, 64))
+        h[special] = g.choice([-1.0, 0.0, np.nan, np.inf, 1e-300, dt / 8.0, dt / 1023.0 * 8.0,
+                               dt / 2.0], size=special.size)
+        hd = torch.from_numpy(h).cuda()
+        order = torch.full((m,), -1, dtype=torch.int32, device="cuda")
+        A.adm1_cost_order(ctx.handle, hd, dt, m, order)
+        torch.cuda.synchronize()
+        o = order.cpu().numpy().astype(np.int64)
+        assert np.array_equal(np.sort(o), np.arange(m))
+        k = _cost_bucket(h, dt)[o]
+        assert np.all(np.diff(k) <= 0)
+    with pytest.raises(A.ADM1Error):
+        A.adm1_set_order(ctx.handle, 2)
+
+
+def test_queue_order_does_not_change_results(torch_cuda):
+    """Index order and cost order of the work queue give every particle the
+    same result bit for bit over warm-started coupling steps (2^16 particles,
+    so the queue cycles many times per wave)."""
+    torch = torch_cuda
+    from paper_2311_08927_amd import adm1 as A
+    w = W.batched_population(1 << 16, seed=11)
+    runs = {}
+    for mode in (A.ORDER_INDEX, A.ORDER_COST):
+        ctx = make_ctx(w.ld, variant=A.VARIANT_SPARSE2)
+        A.adm1_set_order(ctx.handle, mode)
+        dw = DeviceWorkload(w)
+        snaps = []
+        for k in range(3):
+            dw.set_D(w.D_at(k))
+            ctx.step(dw.X, dw.T, dw.D, dw.fidx, dw.S_in, w.dt, n=w.n, H=dw.H, hlast=dw.hlast,
+                     status=dw.status, nsteps=dw.nsteps)
+            torch.cuda.synchronize()
+            snaps.append([t.cpu().numpy().copy() for t in (dw.X, dw.H, dw.hlast, dw.status,
+                                                           dw.nsteps)])
+        runs[mode] = snaps
+    for a, b in zip(runs[A.ORDER_INDEX], runs[A.ORDER_COST]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y, equal_nan=True)
+    assert int((runs[A.ORDER_COST][-1][3] != 0).sum()) == 0
