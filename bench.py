@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--train-epochs", type=int, default=24)
     ap.add_argument("--gate-ion", type=float, default=1e-2,
                     help="surrogate gate: tolerance of the proposed ions and S_h2")
-    ap.add_argument("--gate-closure", type=float, default=1e-3,
+    ap.add_argument("--gate-closure", type=float, default=5e-4,
                     help="surrogate gate: tolerance of the COD / nitrogen closure")
     ap.add_argument("--burn-in", type=int, default=2,
                     help="surrogate path: untimed FP64 steps before the comparison")

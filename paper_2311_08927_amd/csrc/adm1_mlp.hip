@@ -69,17 +69,32 @@ __device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c)
 
 // GELU with a branch-free erf: Abramowitz & Stegun, Handbook of
 // Mathematical Functions, eq. 7.1.26 (|error| <= 1.5e-7 on the real line),
-// odd extension to negative arguments.
+// erf(x) = 1 - P(t) exp(-x^2), t = 1 / (1 + p x), x >= 0, odd extension.
+// Rearranged as z Phi(z) = (z + |z|) / 2 - |z| t q(t) exp(-z^2 / 2), with
+// q = P / (2 t) (coefficients halved) and p / sqrt(2) folded into t: two
+// transcendentals and eleven other operations.
 __device__ __forceinline__ float gelu_fast(float z)
 {
-    const float x = fabsf(z) * 0.70710678118654752f;
-    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
-    const float poly =
-        t * (0.254829592f +
-             t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-    const float erf_abs = 1.0f - poly * __expf(-x * x);
-    const float erf_z = copysignf(erf_abs, z);
-    return 0.5f * z * (1.0f + erf_z);
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
+    const float q =
+        0.127414796f + t * (-0.142248368f + t * (0.7107068705f + t * (-0.7265760135f +
+                                                                     t * 0.5307027145f)));
+    // exp(-z^2/2) = 2^(-(z k)^2), k = sqrt(log2(e) / 2)
+    const float y = z * 0.84932180028801904f;
+    const float e = __builtin_amdgcn_exp2f(-(y * y));
+    return fmaf(-q, az * t * e, 0.5f * (z + az));
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values to packed BF16 with the hardware conversion (round to
+// nearest even, NaN stays NaN), low half first.
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
+{
+    const bf16x2 v = __builtin_convertvector(f32x2{lo, hi}, bf16x2);
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -94,8 +109,14 @@ __device__ __forceinline__ float gelu_fast(float z)
 // 8-byte LDS write (16 bytes for FP32 outputs).
 // A block of 256 threads owns 64 rows; the activations of all five layers
 // stay in two 64 x 264 BF16 LDS buffers (67.6 KB: two blocks per CU).
-// Wave w owns the feature tiles [w CTW, (w + 1) CTW) of a layer and all
-// four row tiles; weight fragments are loaded one k-step ahead.
+// Wave w owns the feature tiles [w CTW, (w + 1) CTW) of a layer: it loads
+// their weight fragments for every k-step into registers once per layer,
+// then runs the four 16-row tiles one after the other; a tile's epilogue
+// (bias, GELU, BF16 packing) is plain straight-line VALU work that the
+// scheduler interleaves with the next tile's matrix instructions.  The
+// per-particle GELU work (1,024 evaluations) costs more VALU cycles than
+// the 215,296 MACs cost matrix-core cycles, so this overlap bounds the
+// kernel.
 // ---------------------------------------------------------------------------
 constexpr int TM = 64;       // rows per block
 constexpr int RT = TM / 16;  // row tiles
@@ -108,14 +129,13 @@ struct FwdArgs {
     const uint16_t* WT[5];
     const float* b[5];
     float* Y;            // [n][48] FP32
-    float* zsave[4];     // [n][256] FP32 pre-activations (nullable)
-    uint16_t* hsave[4];  // [n][256] BF16 activations (nullable)
+    float* zsave[4];     // [n][256] FP32 pre-activations (with SAVE)
+    uint16_t* hsave[4];  // [n][256] BF16 activations (with SAVE)
 };
 
-typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
-
-// One layer: out[TM][NOUT] = act(in[TM][K] W + b).
-template <int K, int NOUT, bool LAST>
+// One layer: out[TM][NOUT] = act(in[TM][K] W + b).  SAVE also writes the
+// pre-activations and activations of rows < n for the backward pass.
+template <int K, int NOUT, bool LAST, bool SAVE>
 __device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const uint16_t* in,
                                           uint16_t* out, int64_t row0)
 {
@@ -124,64 +144,57 @@ __device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const uin
     constexpr int CTW = (CT + 3) / 4;             // per wave
     constexpr int KS = K / 32;                    // k-steps
     const int c0 = w * CTW;
-    f32x4 acc[RT][CTW];
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int c = 0; c < CTW; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (c0 >= CT) return;                         // idle wave of a narrow layer
+    const int kq = 8 * (lane >> 4), li = lane & 15, fq = 4 * (lane >> 4);
     const uint16_t* WT = a.WT[layer];
-    const int kq = 8 * (lane >> 4), li = lane & 15;
-    s16x8 wnext[CTW];
-#pragma unroll
-    for (int c = 0; c < CTW; ++c)
-        wnext[c] = (c0 + c < CT) ? *(const s16x8*)(WT + (int64_t)((c0 + c) * 16 + li) * K + kq)
-                                 : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int k0 = ks * 32;
-        s16x8 wf[CTW];
-#pragma unroll
-        for (int c = 0; c < CTW; ++c) {
-            wf[c] = wnext[c];
-            if (ks + 1 < KS && c0 + c < CT)
-                wnext[c] = *(const s16x8*)(WT + (int64_t)((c0 + c) * 16 + li) * K + k0 + 32 + kq);
-        }
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-            const s16x8 hf = *(const s16x8*)(in + (r * 16 + li) * LDH + k0 + kq);
-#pragma unroll
-            for (int c = 0; c < CTW; ++c) acc[r][c] = mfma32(wf[c], hf, acc[r][c]);
-        }
-    }
-    const float* bias = a.b[layer];
-    const int fq = 4 * (lane >> 4);
+    s16x8 wf[CTW][KS];
+    f32x4 bc[CTW];
 #pragma unroll
     for (int c = 0; c < CTW; ++c) {
-        if (c0 + c >= CT) continue;
-        const int f = (c0 + c) * 16 + fq;      // first of this lane's four features
-        const f32x4 bc = *(const f32x4*)(bias + f);
+        const bool live = c0 + c < CT;
+        const uint16_t* wrow = WT + (int64_t)((c0 + c) * 16 + li) * K + kq;
 #pragma unroll
-        for (int r = 0; r < RT; ++r) {
-            const int row = r * 16 + li;
-            const int64_t grow = row0 + row;
-            const f32x4 z = acc[r][c] + bc;
+        for (int ks = 0; ks < KS; ++ks)
+            wf[c][ks] = live ? *(const s16x8*)(wrow + ks * 32) : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        bc[c] = live ? *(const f32x4*)(a.b[layer] + (c0 + c) * 16 + fq)
+                     : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        f32x4 acc[CTW];
+#pragma unroll
+        for (int c = 0; c < CTW; ++c) acc[c] = bc[c];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const s16x8 hf = *(const s16x8*)(in + (r * 16 + li) * LDH + ks * 32 + kq);
+#pragma unroll
+            for (int c = 0; c < CTW; ++c) acc[c] = mfma32(wf[c][ks], hf, acc[c]);
+        }
+        const int row = r * 16 + li;
+        const int64_t grow = row0 + row;
+#pragma unroll
+        for (int c = 0; c < CTW; ++c) {
+            if (c0 + c >= CT) continue;
+            const int f = (c0 + c) * 16 + fq;  // first of this lane's four features
+            const f32x4 z = acc[c];
             if (LAST) {
                 if (grow < a.n) *(f32x4*)(a.Y + grow * 48 + f) = z;
             } else {
-                u16x4 hb;
-#pragma unroll
-                for (int t = 0; t < 4; ++t) hb[t] = f2bf(gelu_fast(z[t]));
-                *(u16x4*)(out + row * LDH + f) = hb;
-                if (grow < a.n) {
-                    if (a.zsave[layer]) *(f32x4*)(a.zsave[layer] + grow * 256 + f) = z;
-                    if (a.hsave[layer]) *(u16x4*)(a.hsave[layer] + grow * 256 + f) = hb;
+                uint2 hb;
+                hb.x = pack_bf16(gelu_fast(z[0]), gelu_fast(z[1]));
+                hb.y = pack_bf16(gelu_fast(z[2]), gelu_fast(z[3]));
+                *(uint2*)(out + row * LDH + f) = hb;
+                if (SAVE && grow < a.n) {
+                    *(f32x4*)(a.zsave[layer] + grow * 256 + f) = z;
+                    *(uint2*)(a.hsave[layer] + grow * 256 + f) = hb;
                 }
             }
         }
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_mlp_fwd(FwdArgs a)
+template <bool SAVE>
+__global__ void __launch_bounds__(kThreads, 2) k_mlp_fwd(FwdArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint16_t buf0[TM * LDH];
     __shared__ __attribute__((aligned(16))) uint16_t buf1[TM * LDH];
@@ -195,15 +208,15 @@ __global__ void __launch_bounds__(kThreads) k_mlp_fwd(FwdArgs a)
         *(s16x8*)(buf0 + row * LDH + q) = v;
     }
     __syncthreads();
-    fwd_layer<64, 256, false>(a, 0, buf0, buf1, row0);
+    fwd_layer<64, 256, false, SAVE>(a, 0, buf0, buf1, row0);
     __syncthreads();
-    fwd_layer<256, 256, false>(a, 1, buf1, buf0, row0);
+    fwd_layer<256, 256, false, SAVE>(a, 1, buf1, buf0, row0);
     __syncthreads();
-    fwd_layer<256, 256, false>(a, 2, buf0, buf1, row0);
+    fwd_layer<256, 256, false, SAVE>(a, 2, buf0, buf1, row0);
     __syncthreads();
-    fwd_layer<256, 256, false>(a, 3, buf1, buf0, row0);
+    fwd_layer<256, 256, false, SAVE>(a, 3, buf1, buf0, row0);
     __syncthreads();
-    fwd_layer<256, 48, true>(a, 4, buf0, buf1, row0);
+    fwd_layer<256, 48, true, SAVE>(a, 4, buf0, buf1, row0);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,7 +466,10 @@ hipError_t mlp_forward(const MlpDev& m, const uint16_t* X, int64_t n, float* Y, 
         a.hsave[l] = save ? m.h[l] : nullptr;
     }
     const unsigned grid = (unsigned)((n + TM - 1) / TM);
-    hipLaunchKernelGGL(k_mlp_fwd, dim3(grid), dim3(kThreads), 0, s, a);
+    if (save)
+        hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(grid), dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_mlp_fwd<false>, dim3(grid), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -37,6 +37,8 @@ using namespace adm1_abi;
 namespace adm1 {
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 struct GateConsts {
     double cod_w[NX];    // COD weight of each state row (liquid, headspace)
     double n_w[NX];      // nitrogen content of each state row
@@ -79,6 +81,9 @@ struct NullSink {
     __device__ void operator()(int, double) const {}
 };
 
+// Every loop has a fixed trip count and is unrolled, so the per-particle
+// arrays live in registers (a loop with an early exit would put them in
+// scratch memory); the network's output row is read as nine 16-byte loads.
 __global__ void __launch_bounds__(256) k_gate(GateArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -88,6 +93,7 @@ __global__ void __launch_bounds__(256) k_gate(GateArgs a)
         const GateConsts& g = a.g;
         double x0[NX], xh[NX];
         bool ok = true;
+#pragma unroll
         for (int k = 0; k < NX; ++k) {
             x0[k] = a.state[k * a.ld + i];
             ok = ok && isfinite(x0[k]);
@@ -95,15 +101,27 @@ __global__ void __launch_bounds__(256) k_gate(GateArgs a)
         const double T = a.T[i], D = a.D[i];
         const int fi = a.fidx[i];
         ok = ok && isfinite(T) && T > 0.0 && isfinite(D) && fi >= 0 && fi < a.n_feed;
-        for (int k = 0; k < kMlpOut && ok; ++k) {
-            const double d = (double)a.Y[i * kMlpOutPad + k] * g.out_sd[k] + g.out_mean[k];
-            ok = isfinite(d) && fabs(d) < g.max_dlog;
+        float yv[36];
+        {
+            const f32x4* yrow = (const f32x4*)(a.Y + i * kMlpOutPad);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const f32x4 v = yrow[q];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) yv[4 * q + t] = v[t];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kMlpOut; ++k) {
+            const double d = (double)yv[k] * g.out_sd[k] + g.out_mean[k];
+            ok = ok && isfinite(d) && fabs(d) < g.max_dlog;
             xh[k] = fmax(x0[k], g.floor_[k]) * exp(d);
         }
         if (ok) {
             const double* sin = a.S_in + (int64_t)fi * NLIQ;
             const TConst c = tconst(p, T);
             double y[NY];
+#pragma unroll
             for (int k = 0; k < NY; ++k) y[k] = xh[state_row(k)];
             double H = a.H ? a.H[i] : -1.0;
             double Sh2 = xh[ROW_SH2];
@@ -119,6 +137,7 @@ __global__ void __launch_bounds__(256) k_gate(GateArgs a)
                 ion[5] = c.K_a_co2 * y[SIC] / (c.K_a_co2 + H);
                 ion[6] = c.K_a_IN * y[SIN] / (c.K_a_IN + H);
                 double worst = 0.0;
+#pragma unroll
                 for (int k = 0; k < 7; ++k) {
                     const int row = k == 0 ? ROW_SH2 : 25 + k;
                     const double sc = fmax(fabs(ion[k]), 100.0 * g.floor_[row]);
@@ -127,13 +146,16 @@ __global__ void __launch_bounds__(256) k_gate(GateArgs a)
                 ok = worst < g.tol_ion;
                 // closure of COD and nitrogen over the interval
                 double cin = 0.0, nin = 0.0;
+#pragma unroll
                 for (int k = 0; k < NLIQ; ++k) {
                     cin += g.cod_in_w[k] * sin[k];
                     nin += g.n_in_w[k] * sin[k];
                 }
                 xh[ROW_SH2] = Sh2;
+#pragma unroll
                 for (int k = 0; k < 6; ++k) xh[26 + k] = ion[1 + k];
                 double C0 = 0.0, C1 = 0.0, N0 = 0.0, N1 = 0.0, L0 = 0.0, L1 = 0.0;
+#pragma unroll
                 for (int k = 0; k < NX; ++k) {
                     C0 += g.cod_w[k] * x0[k];
                     C1 += g.cod_w[k] * xh[k];
@@ -159,6 +181,7 @@ __global__ void __launch_bounds__(256) k_gate(GateArgs a)
                     fmax(0.0, fmax(a.dt * Fn_lo - dN, dN - a.dt * Fn_hi)) / fabs(N0);
                 ok = ok && rc < g.tol_closure && rn < g.tol_closure;
                 if (ok) {
+#pragma unroll
                     for (int k = 0; k < NX; ++k) a.state[k * a.ld + i] = xh[k];
                     if (a.H) a.H[i] = H;
                     a.status[i] = 0;
