@@ -213,7 +213,8 @@ int adm1_set_launch(adm1_ctx *ctx, int32_t variant, int32_t blocks_per_cu);
  *   ADM1_ORDER_INDEX: 0..n-1.
  *   ADM1_ORDER_COST (default): the permutation of adm1_cost_order on
  *     aux->h_last, i.e. expected step count dt / h_last, largest first, cold
- *     particles first of all.  Used when aux and aux->h_last are given.
+ *     particles first of all.  Used when aux and aux->h_last are given, by
+ *     adm1_step_particles and for the fallback list of adm1_surrogate_step.
  * A particle's result does not depend on the order.  Returns ADM1_E_OPTS for
  * another mode.  Synchronous (no device work). */
 enum { ADM1_ORDER_INDEX = 0, ADM1_ORDER_COST = 1 };

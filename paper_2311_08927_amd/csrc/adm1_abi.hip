@@ -380,8 +380,8 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
         // expensive particles first (predicted by the previous interval's
         // last step size) so that the queue's tail is made of cheap ones
         if (ctx->order_mode == ADM1_ORDER_COST && a.hlast && n <= INT32_MAX) {
-            rc = hip_rc(adm1::launch_cost_order(a.hlast, n, dt_days, ctx->d_order_work,
-                                                ctx->d_order, s));
+            rc = hip_rc(adm1::launch_cost_order(a.hlast, nullptr, nullptr, n, dt_days,
+                                                ctx->d_order_work, ctx->d_order, s));
             if (rc) return rc;
             a.index = ctx->d_order;
             a.index_count = ctx->d_order_work + 2 * adm1::kOrderBuckets;
@@ -409,8 +409,8 @@ int adm1_cost_order(adm1_ctx* ctx, const double* h_last, double dt_days, int64_t
     if (n < 0 || n > INT32_MAX) return ADM1_E_SIZE;
     if (!(dt_days > 0.0) || !std::isfinite(dt_days)) return ADM1_E_DT;
     if (!is_device(h_last) || !is_device(order)) return ADM1_E_NOT_DEVICE;
-    return hip_rc(adm1::launch_cost_order(h_last, n, dt_days, ctx->d_order_work, order,
-                                          (hipStream_t)stream));
+    return hip_rc(adm1::launch_cost_order(h_last, nullptr, nullptr, n, dt_days,
+                                          ctx->d_order_work, order, (hipStream_t)stream));
 }
 
 int adm1_gas_flux(adm1_ctx* ctx, const double* state, int64_t ld, const double* temp_K,

@@ -57,14 +57,17 @@ struct GasArgs {
 hipError_t launch_step1(const StepArgs& a, int rate_precision, bool sparse, hipStream_t s);
 hipError_t launch_step_sparse2(const StepArgs& a, int rate_precision, int blocks_per_cu,
                                hipStream_t s);
-// Cost order of the work queue: order[0..n-1] = particles by non-increasing
+// Cost order of the work queue: order[0..len-1] = particles by non-increasing
 // bucket min(floor(kOrderRes dt / hlast[i]), kOrderBuckets-1) (the last
-// bucket also for hlast[i] <= 0 or NaN).  work: int32 [2 kOrderBuckets + 1],
-// zero in its first kOrderBuckets entries before the first call (left so);
-// work[2 kOrderBuckets] receives n, the list length read by the queue.
+// bucket also for hlast[i] <= 0 or NaN).  Without a list the particles are
+// 0..n-1 (len = n); with one they are list[0..len-1], len = min(*list_count,
+// n) read on the device (n is then the list's capacity).  work: int32
+// [2 kOrderBuckets + 1], zero in its first kOrderBuckets entries before the
+// first call (left so); work[2 kOrderBuckets] receives len for the queue.
 constexpr int kOrderBuckets = 1024;
 constexpr double kOrderRes = 8.0;
-hipError_t launch_cost_order(const double* hlast, int64_t n, double dt, int32_t* work,
+hipError_t launch_cost_order(const double* hlast, const int32_t* list,
+                             const int32_t* list_count, int64_t n, double dt, int32_t* work,
                              int32_t* order, hipStream_t s);
 hipError_t launch_rhs(const RhsArgs& a, int rate_precision, hipStream_t s);
 hipError_t launch_jacobian(const RhsArgs& a, double* J, hipStream_t s);

@@ -598,6 +598,15 @@ int adm1_surrogate_step(adm1_surrogate* s, double* state, int64_t ld, const doub
     a.status = status; a.nsteps = nsteps; a.queue = ctx->d_queue;
     a.index = s->fb_idx; a.index_count = cnt;
     a.pdev = ctx->d_params;
+    // the fallback list in expected-cost order, as the full step orders its
+    // queue (rejected particles are the stiff ones: the tail matters most)
+    if (ctx->order_mode == ADM1_ORDER_COST && a.hlast) {
+        rc = hip_rc(adm1::launch_cost_order(a.hlast, s->fb_idx, cnt, n, dt_days,
+                                            ctx->d_order_work, ctx->d_order, st));
+        if (rc) return rc;
+        a.index = ctx->d_order;
+        a.index_count = ctx->d_order_work + 2 * adm1::kOrderBuckets;
+    }
     return hip_rc(adm1::launch_step_sparse2(a, ctx->opts.rate_precision, ctx->tuned_blocks_per_cu,
                                             st));
 }
