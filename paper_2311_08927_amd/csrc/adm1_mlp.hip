@@ -109,9 +109,10 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
 // 8-byte LDS write (16 bytes for FP32 outputs).
 // A block of 256 threads owns 64 rows; the activations of all five layers
 // stay in two 64 x 264 BF16 LDS buffers (67.6 KB: two blocks per CU).
-// Wave w owns the feature tiles [w CTW, (w + 1) CTW) of a layer: it loads
-// their weight fragments for every k-step into registers once per layer,
-// then runs the four 16-row tiles one after the other; a tile's epilogue
+// Wave w owns the feature tiles [w CTW, (w + 1) CTW) of a layer: it holds
+// their weight fragments for every k-step in registers (requested while the
+// previous layer finishes), then runs the four 16-row tiles one after the
+// other; a tile's epilogue
 // (bias, GELU, BF16 packing) is plain straight-line VALU work that the
 // scheduler interleaves with the next tile's matrix instructions.  The
 // per-particle GELU work (1,024 evaluations) costs more VALU cycles than
@@ -121,7 +122,9 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
 constexpr int TM = 64;       // rows per block
 constexpr int RT = TM / 16;  // row tiles
 constexpr int LDH = 264;     // LDS row stride (BF16 elements): 528 B, 16-byte aligned
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;    // generic GEMM
+constexpr int kFwdWaves = 8;     // forward: waves per block
+constexpr int kFwdThreads = 64 * kFwdWaves;
 
 struct FwdArgs {
     const uint16_t* X;   // [n][64] BF16
@@ -133,43 +136,71 @@ struct FwdArgs {
     uint16_t* hsave[4];  // [n][256] BF16 activations (with SAVE)
 };
 
-// One layer: out[TM][NOUT] = act(in[TM][K] W + b).  SAVE also writes the
-// pre-activations and activations of rows < n for the backward pass.
-template <int K, int NOUT, bool LAST, bool SAVE>
-__device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const uint16_t* in,
-                                          uint16_t* out, int64_t row0)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    constexpr int CT = NOUT / 16;                 // feature tiles
-    constexpr int CTW = (CT + 3) / 4;             // per wave
-    constexpr int KS = K / 32;                    // k-steps
-    const int c0 = w * CTW;
-    if (c0 >= CT) return;                         // idle wave of a narrow layer
-    const int kq = 8 * (lane >> 4), li = lane & 15, fq = 4 * (lane >> 4);
-    const uint16_t* WT = a.WT[layer];
+// A wave's weight fragments and biases for one layer: feature tiles
+// [c0, c0 + CTW) of W^T, every k-step.
+template <int K, int NOUT>
+struct LayerW {
+    static constexpr int CT = NOUT / 16;          // feature tiles
+    static constexpr int CTW = (CT + kFwdWaves - 1) / kFwdWaves;  // per wave
+    static constexpr int KS = K / 32;             // k-steps
     s16x8 wf[CTW][KS];
     f32x4 bc[CTW];
+};
+
+// Issue order = use order (bias, then k-step by k-step), so the first matrix
+// instructions wait only for the first loads (the memory counter retires
+// loads in order).  Tiles past the layer's width (the idle wave of the
+// narrow last layer) load the last tile again: no branch, and their results
+// are never stored.
+template <int K, int NOUT>
+__device__ __forceinline__ void load_layer(const FwdArgs& a, int layer, LayerW<K, NOUT>& w)
+{
+    using L = LayerW<K, NOUT>;
+    const int lane = threadIdx.x & 63, c0 = (threadIdx.x >> 6) * L::CTW;
+    const int kq = 8 * (lane >> 4), li = lane & 15, fq = 4 * (lane >> 4);
+    const uint16_t* WT = a.WT[layer];
+    int ct[L::CTW];
 #pragma unroll
-    for (int c = 0; c < CTW; ++c) {
-        const bool live = c0 + c < CT;
-        const uint16_t* wrow = WT + (int64_t)((c0 + c) * 16 + li) * K + kq;
+    for (int c = 0; c < L::CTW; ++c) ct[c] = c0 + c < L::CT ? c0 + c : L::CT - 1;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            wf[c][ks] = live ? *(const s16x8*)(wrow + ks * 32) : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
-        bc[c] = live ? *(const f32x4*)(a.b[layer] + (c0 + c) * 16 + fq)
-                     : f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int c = 0; c < L::CTW; ++c) w.bc[c] = *(const f32x4*)(a.b[layer] + ct[c] * 16 + fq);
+#pragma unroll
+    for (int ks = 0; ks < L::KS; ++ks)
+#pragma unroll
+        for (int c = 0; c < L::CTW; ++c)
+            w.wf[c][ks] = *(const s16x8*)(WT + (int64_t)(ct[c] * 16 + li) * K + ks * 32 + kq);
+}
+
+// One layer: out[TM][NOUT] = act(in[TM][K] W + b) with the weights in `w`.
+// Once the last tile's matrix instructions are issued, the next layer's
+// weights are requested into `next` (layer + 1), so their latency overlaps
+// the last epilogue and the barrier.  SAVE also writes the pre-activations
+// and activations of rows < n for the backward pass.
+template <int K, int NOUT, bool LAST, bool SAVE, int NK, int NNOUT>
+__device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const LayerW<K, NOUT>& w,
+                                          LayerW<NK, NNOUT>& next, const uint16_t* in,
+                                          uint16_t* out, int64_t row0)
+{
+    using L = LayerW<K, NOUT>;
+    constexpr int CT = L::CT, CTW = L::CTW, KS = L::KS;
+    const int lane = threadIdx.x & 63, c0 = (threadIdx.x >> 6) * CTW;
+    const int kq = 8 * (lane >> 4), li = lane & 15, fq = 4 * (lane >> 4);
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
         f32x4 acc[CTW];
 #pragma unroll
-        for (int c = 0; c < CTW; ++c) acc[c] = bc[c];
+        for (int c = 0; c < CTW; ++c) acc[c] = w.bc[c];
+        // the idle waves of the narrow last layer skip its matrix work
+        if (!LAST || c0 < CT) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const s16x8 hf = *(const s16x8*)(in + (r * 16 + li) * LDH + ks * 32 + kq);
+            for (int ks = 0; ks < KS; ++ks) {
+                const s16x8 hf = *(const s16x8*)(in + (r * 16 + li) * LDH + ks * 32 + kq);
 #pragma unroll
-            for (int c = 0; c < CTW; ++c) acc[c] = mfma32(wf[c][ks], hf, acc[c]);
+                for (int c = 0; c < CTW; ++c) acc[c] = mfma32(w.wf[c][ks], hf, acc[c]);
+            }
         }
+        if (!LAST && r == RT - 1) load_layer<NK, NNOUT>(a, layer + 1, next);
+        if (c0 >= CT) continue;
         const int row = r * 16 + li;
         const int64_t grow = row0 + row;
 #pragma unroll
@@ -194,13 +225,17 @@ __device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const uin
 }
 
 template <bool SAVE>
-__global__ void __launch_bounds__(kThreads, 2) k_mlp_fwd(FwdArgs a)
+__global__ void __launch_bounds__(kFwdThreads, 2) k_mlp_fwd(FwdArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint16_t buf0[TM * LDH];
     __shared__ __attribute__((aligned(16))) uint16_t buf1[TM * LDH];
     const int64_t row0 = (int64_t)blockIdx.x * TM;
+    LayerW<64, 256> w0;
+    LayerW<256, 256> wa, wb;
+    LayerW<256, 48> w4;
+    load_layer<64, 256>(a, 0, w0);
     // input tile: 64 rows x 64 features, 16 bytes per load
-    for (int e = threadIdx.x; e < TM * 8; e += kThreads) {
+    for (int e = threadIdx.x; e < TM * 8; e += kFwdThreads) {
         const int row = e >> 3, q = (e & 7) * 8;
         const int64_t grow = row0 + row;
         s16x8 v = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
@@ -208,15 +243,15 @@ __global__ void __launch_bounds__(kThreads, 2) k_mlp_fwd(FwdArgs a)
         *(s16x8*)(buf0 + row * LDH + q) = v;
     }
     __syncthreads();
-    fwd_layer<64, 256, false, SAVE>(a, 0, buf0, buf1, row0);
+    fwd_layer<64, 256, false, SAVE>(a, 0, w0, wa, buf0, buf1, row0);
     __syncthreads();
-    fwd_layer<256, 256, false, SAVE>(a, 1, buf1, buf0, row0);
+    fwd_layer<256, 256, false, SAVE>(a, 1, wa, wb, buf1, buf0, row0);
     __syncthreads();
-    fwd_layer<256, 256, false, SAVE>(a, 2, buf0, buf1, row0);
+    fwd_layer<256, 256, false, SAVE>(a, 2, wb, wa, buf0, buf1, row0);
     __syncthreads();
-    fwd_layer<256, 256, false, SAVE>(a, 3, buf1, buf0, row0);
+    fwd_layer<256, 256, false, SAVE>(a, 3, wa, w4, buf1, buf0, row0);
     __syncthreads();
-    fwd_layer<256, 48, true, SAVE>(a, 4, buf0, buf1, row0);
+    fwd_layer<256, 48, true, SAVE>(a, 4, w4, w4, buf0, buf1, row0);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,9 +502,9 @@ hipError_t mlp_forward(const MlpDev& m, const uint16_t* X, int64_t n, float* Y, 
     }
     const unsigned grid = (unsigned)((n + TM - 1) / TM);
     if (save)
-        hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(grid), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(grid), dim3(kFwdThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(k_mlp_fwd<false>, dim3(grid), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_mlp_fwd<false>, dim3(grid), dim3(kFwdThreads), 0, s, a);
     return hipGetLastError();
 }
 
