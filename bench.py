@@ -74,6 +74,8 @@ def parse():
                     help="surrogate gate: tolerance of the proposed ions and S_h2")
     ap.add_argument("--gate-closure", type=float, default=5e-4,
                     help="surrogate gate: tolerance of the COD / nitrogen closure")
+    ap.add_argument("--calibrate", type=int, default=1, choices=[0, 1],
+                    help="surrogate: shift the output biases by the mean validation residual")
     ap.add_argument("--burn-in", type=int, default=2,
                     help="surrogate path: untimed FP64 steps before the comparison")
     ap.add_argument("--variant", type=int, default=-1)
@@ -306,6 +308,13 @@ def surrogate_main(args):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     n_train_steps = args.train_epochs * (X.shape[0] // 8192)
+    shift = np.zeros(35)
+    if args.calibrate:
+        # held-out half of the validation rows sets the output biases, the
+        # other half measures the validation error
+        half = Xv.shape[0] // 2
+        shift = S.calibrate_output_bias(sur, Xv[:half], Tv[:half])
+        Xv, Tv = Xv[half:], Tv[half:]
     val_mse = float(((sur.forward(Xv)[:, :35] - Tv) ** 2).mean())
     del X, Tg, Xv, Tv
     torch.cuda.empty_cache()
@@ -447,6 +456,7 @@ def surrogate_main(args):
                              "steps": n_train_steps, "seconds": train_s,
                              "data_seconds": gen_s, "loss_first_last": [hist[0], hist[-1]],
                              "val_mse": val_mse,
+                             "output_bias_shift_max": float(np.abs(shift).max()),
                              "train_flop_per_s": 3 * mlp_flop / wd.n * 8192 *
                              n_train_steps / train_s}},
     }

@@ -41,19 +41,27 @@ struct MlpDev {
     const uint16_t* WT[kMlpLayers];   // BF16 [out_pad][in_pad]
     const float* bias[kMlpLayers];    // FP32 [out_pad] (inside the master vector)
     float* z[4];                      // saved pre-activations [B][256] (training)
-    uint16_t* h[4];                   // saved activations [B][256] (training)
+    uint16_t* hT[4];                  // saved activations, transposed [256][ldt] (training)
+    uint16_t* xT;                     // saved input, transposed [64][ldt] (training)
+    int64_t ldt;                      // row length of the transposed saves: B rounded up to 32
 };
+
+constexpr int kColsumChunks = 32;     // row chunks of the bias-gradient column sums
 
 hipError_t mlp_forward(const MlpDev& m, const uint16_t* X, int64_t n, float* Y, bool save,
                        hipStream_t s);
-hipError_t gemm(const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
-                int64_t sbn, float* C, int64_t ldc, int M, int N, int K, int splitk,
-                float* partial, hipStream_t s);
-hipError_t mlp_loss(const float* Y, const float* T, int64_t B, float* dY, uint16_t* dYb,
-                    float* partial, float* loss, hipStream_t s);
-hipError_t gelu_bwd(const float* dH, const float* Z, int64_t cnt, float* dZ, uint16_t* dZb,
-                    hipStream_t s);
-hipError_t colsum(const float* M, int64_t rows, int ld, int cols, float* out, hipStream_t s);
+// C[m][n] = sum_k A[m lda + k] B[n ldb + k]; K % 16 == 0, lda and ldb
+// multiples of 8; with splitk > 1 the partials (splitk M ldc floats) go
+// through `partial` and are added in fixed order.
+hipError_t gemm_tn(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, float* C,
+                   int64_t ldc, int M, int N, int K, int splitk, float* partial, hipStream_t s);
+hipError_t mlp_loss(const float* Y, const float* T, int64_t B, int64_t ldt, float* dY,
+                    uint16_t* dYb, uint16_t* dYT, float* partial, float* loss, hipStream_t s);
+hipError_t gelu_bwd(const float* dH, const float* Z, int64_t B, int64_t ldt, float* dZ,
+                    uint16_t* dZb, uint16_t* dZT, hipStream_t s);
+// part: kColsumChunks * cols floats of scratch
+hipError_t colsum(const float* M, int64_t rows, int ld, int cols, float* out, float* part,
+                  hipStream_t s);
 hipError_t adam(float* p, const float* g, float* m, float* v, const uint8_t* mask, int64_t cnt,
                 float lr, float b1, float b2, float eps, int step, hipStream_t s);
 hipError_t pack(const float* W, int in, int out, uint16_t* WT, uint16_t* Wb, hipStream_t s);

@@ -13,14 +13,17 @@
 //                WT[out][in] so each lane's eight k-values are one 16-byte
 //                load; optional saving of pre-activations (FP32) and
 //                activations (BF16) for the backward pass;
-//   k_gemm       generic strided BF16 GEMM (v_mfma_f32_16x16x16_bf16) with
-//                LDS staging and split-K,
-//                used by the backward pass (dH = dZ W^T, dW = H^T dZ);
+//   k_gemm_tn    BF16 GEMM with both operands contiguous along the
+//                contraction (v_mfma_f32_16x16x32_bf16, register-tiled,
+//                split-K): the backward pass dH = dZ W^T and dW = H^T dZ on
+//                the transposed copies the forward and backward kernels save;
 //   k_loss, k_gelu_bwd, k_colsum, k_splitk_sum, k_adam, k_pack: the
 //                elementwise and reduction steps of training;
 //   k_featurize  the network input from the FP64 state.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "adm1_mlp.h"
 
@@ -133,7 +136,9 @@ struct FwdArgs {
     const float* b[5];
     float* Y;            // [n][48] FP32
     float* zsave[4];     // [n][256] FP32 pre-activations (with SAVE)
-    uint16_t* hsave[4];  // [n][256] BF16 activations (with SAVE)
+    uint16_t* hT[4];     // [256][ldt] BF16 activations, transposed (with SAVE)
+    uint16_t* xT;        // [64][ldt] BF16 input, transposed (with SAVE)
+    int64_t ldt;         // row length of the transposed saves, >= n
 };
 
 // A wave's weight fragments and biases for one layer: feature tiles
@@ -215,9 +220,13 @@ __device__ __forceinline__ void fwd_layer(const FwdArgs& a, int layer, const Lay
                 hb.x = pack_bf16(gelu_fast(z[0]), gelu_fast(z[1]));
                 hb.y = pack_bf16(gelu_fast(z[2]), gelu_fast(z[3]));
                 *(uint2*)(out + row * LDH + f) = hb;
-                if (SAVE && grow < a.n) {
-                    *(f32x4*)(a.zsave[layer] + grow * 256 + f) = z;
-                    *(uint2*)(a.hsave[layer] + grow * 256 + f) = hb;
+                if (SAVE && grow < a.n) *(f32x4*)(a.zsave[layer] + grow * 256 + f) = z;
+                if (SAVE && grow < a.ldt) {
+                    uint16_t* ht = a.hT[layer] + (int64_t)f * a.ldt + grow;
+                    ht[0] = (uint16_t)hb.x;
+                    ht[a.ldt] = (uint16_t)(hb.x >> 16);
+                    ht[2 * a.ldt] = (uint16_t)hb.y;
+                    ht[3 * a.ldt] = (uint16_t)(hb.y >> 16);
                 }
             }
         }
@@ -241,6 +250,10 @@ __global__ void __launch_bounds__(kFwdThreads, 2) k_mlp_fwd(FwdArgs a)
         s16x8 v = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
         if (grow < a.n) v = *(const s16x8*)(a.X + grow * 64 + q);
         *(s16x8*)(buf0 + row * LDH + q) = v;
+        if (SAVE && grow < a.ldt) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) a.xT[(int64_t)(q + t) * a.ldt + grow] = (uint16_t)v[t];
+        }
     }
     __syncthreads();
     fwd_layer<64, 256, false, SAVE>(a, 0, w0, wa, buf0, buf1, row0);
@@ -255,68 +268,100 @@ __global__ void __launch_bounds__(kFwdThreads, 2) k_mlp_fwd(FwdArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Generic GEMM: C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m sam + k sak],
-// B(k, n) = B[k sbk + n sbn] (BF16), C FP32 with row stride ldc.  Tile
-// 64 x 64 per block, K in steps of 16 staged through LDS; split-K over
-// gridDim.z writes partial C at C + z * splitc.
+// Backward GEMM, both operands contiguous along the contraction index:
+//   C[m][n] (+ z splitc) = sum_{k in chunk z} A[m lda + k] B[n ldb + k]
+// (BF16 in, FP32 out).  dW = H^T dZ reads the transposed activations and
+// gradients the forward and backward kernels save; dH = dZ W^T reads dZ
+// and W[in][out] as stored.  Each wave owns a 64 x 64 block of C (4 x 4
+// 16 x 16 tiles, 64 accumulator VGPRs) and loads its operand fragments
+// straight from memory (16 bytes per lane, the next k-step's issued before
+// the current one's matrix instructions); a block is 2 x 2 waves.  K is a
+// multiple of 16: a remainder of 16 runs on the 16x16x16 instruction.
+// Rows and columns past M and N load the last valid ones and are not stored.
 // ---------------------------------------------------------------------------
-struct GemmArgs {
+struct TnArgs {
     const uint16_t* A;
-    int64_t sam, sak;
+    int64_t lda;
     const uint16_t* B;
-    int64_t sbk, sbn;
+    int64_t ldb;
     float* C;
     int64_t ldc, splitc;
     int M, N, K, kchunk;
 };
 
-__global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g)
+__global__ void __launch_bounds__(256) k_gemm_tn(TnArgs g)
 {
-    __shared__ uint16_t As[64][20];
-    __shared__ uint16_t Bs[64][20];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int m0 = blockIdx.y * 128 + (w & 1) * 64, n0 = blockIdx.x * 128 + (w >> 1) * 64;
+    if (m0 >= g.M || n0 >= g.N) return;  // no barriers below: a wave may leave
     const int kb = blockIdx.z * g.kchunk;
     const int ke = min(g.K, kb + g.kchunk);
-    const int kq = 4 * (lane >> 4), li = lane & 15;
-    f32x4 acc[4];
+    const int li = lane & 15, q = lane >> 4;
+    const uint16_t* ap[4];
+    const uint16_t* bp[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = kb; k0 < ke; k0 += 16) {
-        // consecutive threads walk the unit-stride index of each operand
-        for (int e = threadIdx.x; e < 64 * 16; e += kThreads) {
-            const int ra = g.sak == 1 ? e >> 4 : e & 63, ka = g.sak == 1 ? e & 15 : e >> 6;
-            const int rb = g.sbk == 1 ? e >> 4 : e & 63, kb2 = g.sbk == 1 ? e & 15 : e >> 6;
-            const int m = m0 + ra, nn = n0 + rb;
-            const int kA = k0 + ka, kB = k0 + kb2;
-            As[ra][ka] =
-                (m < g.M && kA < ke) ? g.A[(int64_t)m * g.sam + (int64_t)kA * g.sak] : 0;
-            Bs[rb][kb2] =
-                (nn < g.N && kB < ke) ? g.B[(int64_t)kB * g.sbk + (int64_t)nn * g.sbn] : 0;
+    for (int t = 0; t < 4; ++t) {
+        ap[t] = g.A + (int64_t)min(m0 + 16 * t + li, g.M - 1) * g.lda;
+        bp[t] = g.B + (int64_t)min(n0 + 16 * t + li, g.N - 1) * g.ldb;
+    }
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kfull = kb + ((ke - kb) / 32) * 32;
+    s16x8 an[4], bn[4];
+    if (kb < kfull) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            an[t] = *(const s16x8*)(ap[t] + kb + 8 * q);
+            bn[t] = *(const s16x8*)(bp[t] + kb + 8 * q);
         }
-        __syncthreads();
-        s16x4 af;
+    }
+    for (int k = kb; k < kfull; k += 32) {
+        s16x8 af[4], bf[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) af[t] = (short)As[w * 16 + li][kq + t];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            s16x4 bf;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) bf[t] = (short)Bs[c * 16 + li][kq + t];
-            acc[c] = mfma16(af, bf, acc[c]);
+        for (int t = 0; t < 4; ++t) {
+            af[t] = an[t];
+            bf[t] = bn[t];
         }
-        __syncthreads();
+        if (k + 32 < kfull) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                an[t] = *(const s16x8*)(ap[t] + k + 32 + 8 * q);
+                bn[t] = *(const s16x8*)(bp[t] + k + 32 + 8 * q);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = mfma32(af[r], bf[c], acc[r][c]);
+    }
+    if (kfull < ke) {  // 16 left
+        s16x4 a4[4], b4[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            a4[t] = *(const s16x4*)(ap[t] + kfull + 4 * q);
+            b4[t] = *(const s16x4*)(bp[t] + kfull + 4 * q);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = mfma16(a4[r], b4[c], acc[r][c]);
     }
     float* C = g.C + (int64_t)blockIdx.z * g.splitc;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int col = n0 + c * 16 + li;
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int row = m0 + w * 16 + kq + t;
-            if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[c][t];
+        for (int c = 0; c < 4; ++c) {
+            const int col = n0 + 16 * c + li;
+            if (col >= g.N) continue;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = m0 + 16 * r + 4 * q + t;
+                if (row < g.M) C[(int64_t)row * g.ldc + col] = acc[r][c][t];
+            }
         }
-    }
 }
 
 // Sum of split-K partials in fixed order: out[i] = sum_z part[z * stride + i].
@@ -329,25 +374,38 @@ __global__ void k_splitk_sum(const float* part, int64_t stride, int S, int64_t c
     out[i] = s;
 }
 
-// MSE loss on the 35 outputs: dY = 2 (Y - T) / (B 35) (FP32 and BF16), and
-// per-block partial sums of the squared error.
+// MSE loss on the 35 outputs: dY = 2 (Y - T) / (B 35) as FP32 [B][48], BF16
+// [B][48] and BF16 transposed [48][ldt] (zero in rows b >= B), and
+// per-block partial sums of the squared error.  A thread owns eight
+// consecutive rows of one column, so the transposed copy is one 16-byte
+// store.
 __global__ void __launch_bounds__(256) k_loss(const float* Y, const float* T, int64_t B,
-                                              float* dY, uint16_t* dYb, float* partial)
+                                              int64_t ldt, float* dY, uint16_t* dYb,
+                                              uint16_t* dYT, float* partial)
 {
     __shared__ float red[256];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b8 = gid / 48;
+    const int c = (int)(gid - b8 * 48);
     float s = 0.f;
-    if (i < B * 48) {
-        const int64_t r = i / 48;
-        const int c = (int)(i - r * 48);
-        float g = 0.f;
-        if (c < 35) {
-            const float d = Y[i] - T[r * 35 + c];
-            s = d * d;
-            g = 2.f * d / (float)(B * 35);
+    if (b8 * 8 < ldt) {
+        s16x8 t8;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int64_t r = b8 * 8 + t;
+            float g = 0.f;
+            if (r < B) {
+                if (c < 35) {
+                    const float d = Y[r * 48 + c] - T[r * 35 + c];
+                    s += d * d;
+                    g = 2.f * d / (float)(B * 35);
+                }
+                dY[r * 48 + c] = g;
+                dYb[r * 48 + c] = f2bf(g);
+            }
+            t8[t] = (short)f2bf(g);
         }
-        dY[i] = g;
-        dYb[i] = f2bf(g);
+        *(s16x8*)(dYT + (int64_t)c * ldt + b8 * 8) = t8;
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -373,32 +431,52 @@ __global__ void __launch_bounds__(256) k_loss_final(const float* partial, int nb
     if (threadIdx.x == 0) loss[0] = red[0] / (float)(B * 35);
 }
 
-// dZ = dH * GELU'(Z), FP32 and BF16 copies.
-__global__ void k_gelu_bwd(const float* dH, const float* Z, int64_t cnt, float* dZ,
-                           uint16_t* dZb)
+// dZ = dH * GELU'(Z) for a [B][256] layer: FP32 and BF16 [B][256] and BF16
+// transposed [256][ldt] (zero in rows b >= B).  A thread owns eight
+// consecutive rows of one column.
+__global__ void __launch_bounds__(256) k_gelu_bwd(const float* dH, const float* Z, int64_t B,
+                                                  int64_t ldt, float* dZ, uint16_t* dZb,
+                                                  uint16_t* dZT)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const float g = dH[i] * gelu_grad(Z[i]);
-    dZ[i] = g;
-    dZb[i] = f2bf(g);
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b8 = gid >> 8;
+    const int c = (int)(gid & 255);
+    if (b8 * 8 >= ldt) return;
+    s16x8 t8;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t r = b8 * 8 + t;
+        uint16_t hb = 0;
+        if (r < B) {
+            const float g = dH[r * 256 + c] * gelu_grad(Z[r * 256 + c]);
+            hb = f2bf(g);
+            dZ[r * 256 + c] = g;
+            dZb[r * 256 + c] = hb;
+        }
+        t8[t] = (short)hb;
+    }
+    *(s16x8*)(dZT + (int64_t)c * ldt + b8 * 8) = t8;
 }
 
-// Column sums in fixed order: out[c] = sum_r M[r * ld + c], r < rows.
+// Column sums in fixed order, first stage: part[z][c] = sum of M[r][c] over
+// the rows of chunk z (64 columns per block, four row phases per column,
+// coalesced 256-byte row reads); k_splitk_sum adds the chunks in order.
 __global__ void __launch_bounds__(256) k_colsum(const float* M, int64_t rows, int ld, int cols,
-                                                float* out)
+                                                int64_t chunk, float* part)
 {
-    __shared__ float red[256];
-    const int c = blockIdx.x;
+    __shared__ float red[4][64];
+    const int cl = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
+    const int64_t r0 = (int64_t)blockIdx.y * chunk;
+    const int64_t r1 = min(rows, r0 + chunk);
     float s = 0.f;
-    for (int64_t r = threadIdx.x; r < rows; r += 256) s += M[r * ld + c];
-    red[threadIdx.x] = s;
+    if (c < cols)
+        for (int64_t r = r0 + ph; r < r1; r += 4) s += M[r * ld + c];
+    red[ph][cl] = s;
     __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && c < cols) out[c] = red[0];
+    if (ph == 0 && c < cols)
+        part[(int64_t)blockIdx.y * cols + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) +
+                                               red[3][cl];
 }
 
 // Adam on the FP32 master parameters (padded entries carry a zero mask).
@@ -498,8 +576,10 @@ hipError_t mlp_forward(const MlpDev& m, const uint16_t* X, int64_t n, float* Y, 
     a.Y = Y;
     for (int l = 0; l < 4; ++l) {
         a.zsave[l] = save ? m.z[l] : nullptr;
-        a.hsave[l] = save ? m.h[l] : nullptr;
+        a.hT[l] = save ? m.hT[l] : nullptr;
     }
+    a.xT = save ? m.xT : nullptr;
+    a.ldt = save ? m.ldt : 0;
     const unsigned grid = (unsigned)((n + TM - 1) / TM);
     if (save)
         hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(grid), dim3(kFwdThreads), 0, s, a);
@@ -508,23 +588,23 @@ hipError_t mlp_forward(const MlpDev& m, const uint16_t* X, int64_t n, float* Y, 
     return hipGetLastError();
 }
 
-hipError_t gemm(const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
-                int64_t sbn, float* C, int64_t ldc, int M, int N, int K, int splitk,
-                float* partial, hipStream_t s)
+hipError_t gemm_tn(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, float* C,
+                   int64_t ldc, int M, int N, int K, int splitk, float* partial, hipStream_t s)
 {
-    GemmArgs g;
-    g.A = A; g.sam = sam; g.sak = sak; g.B = B; g.sbk = sbk; g.sbn = sbn;
-    g.M = M; g.N = N; g.K = K;
+    if (M <= 0 || N <= 0 || K <= 0 || K % 16 != 0 || lda % 8 != 0 || ldb % 8 != 0)
+        return hipErrorInvalidValue;
+    TnArgs g;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.M = M; g.N = N; g.K = K;
+    const dim3 tiles((unsigned)((N + 127) / 128), (unsigned)((M + 127) / 128));
     if (splitk <= 1) {
         g.C = C; g.ldc = ldc; g.splitc = 0; g.kchunk = K;
-        hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64, 1), dim3(kThreads), 0, s,
-                           g);
+        hipLaunchKernelGGL(k_gemm_tn, dim3(tiles.x, tiles.y, 1), dim3(256), 0, s, g);
         return hipGetLastError();
     }
-    const int kchunk = ((K + splitk - 1) / splitk + 15) / 16 * 16;
+    const int kchunk = ((K + splitk - 1) / splitk + 31) / 32 * 32;
     const int S = (K + kchunk - 1) / kchunk;
     g.C = partial; g.ldc = ldc; g.splitc = (int64_t)M * ldc; g.kchunk = kchunk;
-    hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64, S), dim3(kThreads), 0, s, g);
+    hipLaunchKernelGGL(k_gemm_tn, dim3(tiles.x, tiles.y, S), dim3(256), 0, s, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t cnt = (int64_t)M * ldc;
@@ -533,28 +613,37 @@ hipError_t gemm(const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, 
     return hipGetLastError();
 }
 
-hipError_t mlp_loss(const float* Y, const float* T, int64_t B, float* dY, uint16_t* dYb,
-                    float* partial, float* loss, hipStream_t s)
+hipError_t mlp_loss(const float* Y, const float* T, int64_t B, int64_t ldt, float* dY,
+                    uint16_t* dYb, uint16_t* dYT, float* partial, float* loss, hipStream_t s)
 {
-    const int nb = (int)((B * 48 + 255) / 256);
-    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, Y, T, B, dY, dYb, partial);
+    const int nb = (int)((ldt / 8 * 48 + 255) / 256);
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, Y, T, B, ldt, dY, dYb, dYT, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, partial, nb, B, loss);
     return hipGetLastError();
 }
 
-hipError_t gelu_bwd(const float* dH, const float* Z, int64_t cnt, float* dZ, uint16_t* dZb,
-                    hipStream_t s)
+hipError_t gelu_bwd(const float* dH, const float* Z, int64_t B, int64_t ldt, float* dZ,
+                    uint16_t* dZb, uint16_t* dZT, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gelu_bwd, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, dH, Z,
-                       cnt, dZ, dZb);
+    const int64_t threads = ldt / 8 * 256;
+    hipLaunchKernelGGL(k_gelu_bwd, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, dH,
+                       Z, B, ldt, dZ, dZb, dZT);
     return hipGetLastError();
 }
 
-hipError_t colsum(const float* M, int64_t rows, int ld, int cols, float* out, hipStream_t s)
+hipError_t colsum(const float* M, int64_t rows, int ld, int cols, float* out, float* part,
+                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_colsum, dim3(cols), dim3(256), 0, s, M, rows, ld, cols, out);
+    const int64_t nz = std::min<int64_t>(kColsumChunks, std::max<int64_t>(1, rows / 256));
+    const int64_t chunk = (rows + nz - 1) / nz;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((cols + 63) / 64), (unsigned)nz), dim3(256), 0,
+                       s, M, rows, ld, cols, chunk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, part,
+                       (int64_t)cols, (int)nz, (int64_t)cols, out);
     return hipGetLastError();
 }
 

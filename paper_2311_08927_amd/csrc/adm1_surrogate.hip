@@ -234,16 +234,20 @@ struct adm1_surrogate {
     float* Y;          // [n_max][48]
     int32_t* fb_idx;   // [n_max]
     int32_t* fb_count;
-    // training (batch_max rows)
-    float* z[4];
-    uint16_t* h[4];
+    // training (batch_max rows; transposed copies [features][ldt], ldt the
+    // batch rounded up to 32, for the weight-gradient GEMMs)
+    float* z[4];       // pre-activations [B][256]
+    uint16_t* hT[4];   // activations [256][ldt]
+    uint16_t* xT;      // input [64][ldt]
     float* Yt;
     float* dY;
     uint16_t* dYb;
+    uint16_t* dYT;     // [48][ldt]
     float* dH;
     float* dZ;
     uint16_t* dZb;
-    float* split;      // split-K partials
+    uint16_t* dZT;     // [256][ldt]
+    float* split;      // split-K and column-sum partials
     float* lossp;      // loss block partials
     std::vector<void*> allocs;
 };
@@ -313,8 +317,10 @@ MlpDev mlp_dev(const adm1_surrogate* s, bool save)
     }
     for (int l = 0; l < 4; ++l) {
         m.z[l] = save ? s->z[l] : nullptr;
-        m.h[l] = save ? s->h[l] : nullptr;
+        m.hT[l] = save ? s->hT[l] : nullptr;
     }
+    m.xT = save ? s->xT : nullptr;
+    m.ldt = 0;
     return m;
 }
 
@@ -355,12 +361,15 @@ int adm1_surrogate_create(adm1_ctx* ctx, int64_t n_max, int64_t batch_max, adm1_
               dalloc(s, s->floor_, NX) && dalloc(s, s->X, n_max * kMlpInPad) &&
               dalloc(s, s->Y, n_max * kMlpOutPad) && dalloc(s, s->fb_idx, n_max) &&
               dalloc(s, s->fb_count, 64);
+    const int64_t ldt = (B + 31) / 32 * 32;
     for (int l = 0; l < 4 && ok; ++l)
-        ok = dalloc(s, s->z[l], B * kMlpHidden) && dalloc(s, s->h[l], B * kMlpHidden);
-    ok = ok && dalloc(s, s->Yt, B * kMlpOutPad) && dalloc(s, s->dY, B * kMlpOutPad) &&
-         dalloc(s, s->dYb, B * kMlpOutPad) && dalloc(s, s->dH, B * kMlpHidden) &&
+        ok = dalloc(s, s->z[l], B * kMlpHidden) && dalloc(s, s->hT[l], ldt * kMlpHidden);
+    ok = ok && dalloc(s, s->xT, ldt * kMlpInPad) && dalloc(s, s->Yt, B * kMlpOutPad) &&
+         dalloc(s, s->dY, B * kMlpOutPad) && dalloc(s, s->dYb, B * kMlpOutPad) &&
+         dalloc(s, s->dYT, ldt * kMlpOutPad) && dalloc(s, s->dH, B * kMlpHidden) &&
          dalloc(s, s->dZ, B * kMlpHidden) && dalloc(s, s->dZb, B * kMlpHidden) &&
-         dalloc(s, s->split, split) && dalloc(s, s->lossp, (B * kMlpOutPad + 255) / 256 + 1);
+         dalloc(s, s->dZT, ldt * kMlpHidden) && dalloc(s, s->split, split) &&
+         dalloc(s, s->lossp, (B * kMlpOutPad + 255) / 256 + 1);
     if (ok) {
         // zero parameters and moments; mask of the real entries
         std::vector<uint8_t> mask((size_t)np, 0);
@@ -657,24 +666,31 @@ int adm1_surrogate_train_step(adm1_surrogate* s, const uint16_t* X, const float*
     if (step < 1 || !(lr >= 0.0f) || !std::isfinite(lr)) return ADM1_E_OPTS;
     if (!is_device(X) || !is_device(target) || !is_device(loss)) return ADM1_E_NOT_DEVICE;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = mlp_forward(mlp_dev(s, true), X, B, s->Yt, true, st);
-    if (e == hipSuccess) e = mlp_loss(s->Yt, target, B, s->dY, s->dYb, s->lossp, loss, st);
+    const int64_t ldt = (B + 31) / 32 * 32;
+    MlpDev md = mlp_dev(s, true);
+    md.ldt = ldt;
+    hipError_t e = mlp_forward(md, X, B, s->Yt, true, st);
+    if (e == hipSuccess)
+        e = mlp_loss(s->Yt, target, B, ldt, s->dY, s->dYb, s->dYT, s->lossp, loss, st);
     const int Bi = (int)B;
-    const int splitk = (int)std::min<int64_t>(kSplitMax, std::max<int64_t>(1, B / 512));
-    // backward, last layer first; dZ of layer l is (dY, dYb) for l = 4
+    const int splitk = (int)std::min<int64_t>(kSplitMax, std::max<int64_t>(1, ldt / 512));
+    // backward, last layer first; dZ of layer l is (dY, dYb, dYT) for l = 4
     for (int l = kMlpLayers - 1; l >= 0 && e == hipSuccess; --l) {
         const int I = kMlpPadIn[l], O = kMlpPadOut[l];
-        const uint16_t* Ain = l == 0 ? X : s->h[l - 1];
-        const float* dZf = l == kMlpLayers - 1 ? s->dY : s->dZ;
-        const uint16_t* dZh = l == kMlpLayers - 1 ? s->dYb : s->dZb;
+        const uint16_t* AinT = l == 0 ? s->xT : s->hT[l - 1];
+        const bool top = l == kMlpLayers - 1;
+        const float* dZf = top ? s->dY : s->dZ;
+        const uint16_t* dZh = top ? s->dYb : s->dZb;
+        const uint16_t* dZT = top ? s->dYT : s->dZT;
         // dW = A_in^T dZ  ([I][O], contraction over the batch)
-        e = gemm(Ain, 1, I, dZh, O, 1, s->G + mlp_w_offset(l), O, I, O, Bi, splitk, s->split, st);
-        if (e == hipSuccess) e = colsum(dZf, B, O, O, s->G + mlp_b_offset(l), st);
+        e = gemm_tn(AinT, ldt, dZT, ldt, s->G + mlp_w_offset(l), O, I, O, (int)ldt, splitk,
+                    s->split, st);
+        if (e == hipSuccess) e = colsum(dZf, B, O, O, s->G + mlp_b_offset(l), s->split, st);
         if (l == 0 || e != hipSuccess) continue;
         // dH = dZ W^T ([B][I]), then through the GELU of layer l - 1
-        e = gemm(dZh, O, 1, s->Wb + wt_offset(l), 1, O, s->dH, I, Bi, I, O, 1, nullptr, st);
+        e = gemm_tn(dZh, O, s->Wb + wt_offset(l), O, s->dH, I, Bi, I, O, 1, nullptr, st);
         if (e == hipSuccess)
-            e = gelu_bwd(s->dH, s->z[l - 1], B * (int64_t)kMlpHidden, s->dZ, s->dZb, st);
+            e = gelu_bwd(s->dH, s->z[l - 1], B, ldt, s->dZ, s->dZb, s->dZT, st);
     }
     if (e == hipSuccess)
         e = adam(s->P, s->G, s->M, s->V, s->mask, kMlpPadParams, lr, 0.9f, 0.999f, 1e-8f, step,

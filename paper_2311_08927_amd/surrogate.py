@@ -317,6 +317,23 @@ def bf16_to_float(Xb):
     return (Xb.to(torch.int32) << 16).view(torch.float32)
 
 
+def calibrate_output_bias(sur: Surrogate, X, Tg, chunk: int = 1 << 20) -> np.ndarray:
+    """Shift the output layer's biases by minus the network's mean residual
+    (standardised units) on held-out rows (X, Tg): a coherent bias of the
+    predicted increments adds up over a tank of particles and over coupling
+    steps, while per-particle scatter averages out.  Returns the shift."""
+    import torch
+    acc = torch.zeros(OUT, dtype=torch.float64, device=X.device)
+    for a in range(0, X.shape[0], chunk):
+        Y = sur.forward(X[a:a + chunk])[:, :OUT]
+        acc += (Y.double() - Tg[a:a + chunk].double()).sum(dim=0)
+    shift = (acc / max(1, X.shape[0])).cpu().numpy()
+    params, norm = sur.get_weights()
+    params[-OUT:] -= shift.astype(np.float32)
+    sur.set_weights(params, norm)
+    return -shift
+
+
 def train(sur: Surrogate, X, Tg, epochs: int, batch: int = 8192, lr: float = 1e-3,
           seed: int = 4, log=None):
     """Adam on (X, Tg) (device tensors, already standardised) with a cosine
