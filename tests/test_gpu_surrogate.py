@@ -395,3 +395,29 @@ def test_trained_network_beats_untrained(torch_cuda):
     assert fb_t < fb_u
     assert tank_t < tank_u and ph_t < ph_u
     assert res[("trained", 1e-2)][2] <= 1e-3
+
+
+def test_output_bias_calibration_removes_mean_residual(torch_cuda):
+    """calibrate_output_bias moves only the 35 output biases, by minus the
+    mean residual: afterwards the mean residual on the same rows is zero up
+    to FP32 rounding, and the per-row scatter is unchanged."""
+    torch = torch_cuda
+    from paper_2311_08927_amd import surrogate as S
+    ctx, sur = make(4096)
+    p0 = seeded_params(11)
+    sur.set_weights(p0, seeded_norm(5))
+    rng = np.random.default_rng(12)
+    n = 4000
+    bits = np.zeros((n, 64), dtype=np.uint16)
+    bits[:, :38] = M.bf16_bits(rng.standard_normal((n, 38)).astype(np.float32))
+    X = torch.from_numpy(bits.view(np.int16)).cuda()
+    T = torch.from_numpy(rng.standard_normal((n, 35)).astype(np.float32) * 0.1 + 0.3).cuda()
+    r0 = (sur.forward(X)[:, :35] - T).double()
+    shift = S.calibrate_output_bias(sur, X, T, chunk=1536)
+    r1 = (sur.forward(X)[:, :35] - T).double()
+    p1, _ = sur.get_weights()
+    assert np.array_equal(p1[:-35], p0[:-35])
+    assert np.allclose(p1[-35:] - p0[-35:], shift, atol=1e-6)
+    assert np.allclose(shift, -r0.mean(dim=0).cpu().numpy(), atol=1e-6)
+    assert float(r1.mean(dim=0).abs().max()) < 1e-5
+    assert torch.allclose(r1 - r1.mean(dim=0), r0 - r0.mean(dim=0), atol=1e-5)
