@@ -310,32 +310,37 @@ __global__ void __launch_bounds__(256) k_gemm_tn(TnArgs g)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kfull = kb + ((ke - kb) / 32) * 32;
-    s16x8 an[4], bn[4];
-    if (kb < kfull) {
+    // three k-steps of fragments in flight (a ring of register buffers):
+    // a step's loads are issued two steps before its matrix instructions
+    s16x8 fa[3][4], fb[3][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            an[t] = *(const s16x8*)(ap[t] + kb + 8 * q);
-            bn[t] = *(const s16x8*)(bp[t] + kb + 8 * q);
-        }
-    }
-    for (int k = kb; k < kfull; k += 32) {
-        s16x8 af[4], bf[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            af[t] = an[t];
-            bf[t] = bn[t];
-        }
-        if (k + 32 < kfull) {
+    for (int j = 0; j < 3; ++j)
+        if (kb + 32 * j < kfull) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                an[t] = *(const s16x8*)(ap[t] + k + 32 + 8 * q);
-                bn[t] = *(const s16x8*)(bp[t] + k + 32 + 8 * q);
+                fa[j][t] = *(const s16x8*)(ap[t] + kb + 32 * j + 8 * q);
+                fb[j][t] = *(const s16x8*)(bp[t] + kb + 32 * j + 8 * q);
             }
         }
+    for (int k = kb; k < kfull; k += 96) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int j = 0; j < 3; ++j) {
+            const int kj = k + 32 * j;
+            if (kj < kfull) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[r][c] = mfma32(af[r], bf[c], acc[r][c]);
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[r][c] = mfma32(fa[j][r], fb[j][c], acc[r][c]);
+                if (kj + 96 < kfull) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        fa[j][t] = *(const s16x8*)(ap[t] + kj + 96 + 8 * q);
+                        fb[j][t] = *(const s16x8*)(bp[t] + kj + 96 + 8 * q);
+                    }
+                }
+            }
+        }
     }
     if (kfull < ke) {  // 16 left
         s16x4 a4[4], b4[4];
@@ -469,9 +474,18 @@ __global__ void __launch_bounds__(256) k_colsum(const float* M, int64_t rows, in
     const int c = blockIdx.x * 64 + cl;
     const int64_t r0 = (int64_t)blockIdx.y * chunk;
     const int64_t r1 = min(rows, r0 + chunk);
-    float s = 0.f;
-    if (c < cols)
-        for (int64_t r = r0 + ph; r < r1; r += 4) s += M[r * ld + c];
+    // eight running sums per thread (rows r0 + ph + 4 j, j mod 8), added in
+    // a fixed order: independent loads stay in flight
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (c < cols) {
+        int64_t r = r0 + ph;
+        for (; r + 28 < r1; r += 32) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] += M[(r + 4 * j) * ld + c];
+        }
+        for (; r < r1; r += 4) acc[0] += M[r * ld + c];
+    }
+    const float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     red[ph][cl] = s;
     __syncthreads();
     if (ph == 0 && c < cols)
