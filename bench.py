@@ -74,6 +74,10 @@ def parse():
                     help="surrogate gate: tolerance of the proposed ions and S_h2")
     ap.add_argument("--gate-closure", type=float, default=5e-4,
                     help="surrogate gate: tolerance of the COD / nitrogen closure")
+    ap.add_argument("--fair-rtols", type=str, default="1e-2,1e-3,1e-4,1e-5,1e-6",
+                    help="surrogate: looser FP64 tolerances timed on the same field; the "
+                         "loosest one within 1e-3 of the rtol-1e-8 run in tank methane flow "
+                         "and pH (p99) is the fair baseline ('' to skip)")
     ap.add_argument("--calibrate", type=int, default=1, choices=[0, 1],
                     help="surrogate: shift the output biases by the mean validation residual")
     ap.add_argument("--burn-in", type=int, default=2,
@@ -346,7 +350,10 @@ def surrogate_main(args):
     X0, H0, hl0, pos0 = X.clone(), H.clone(), hl.clone(), pos.clone()
     gate = S.adm1_gate(5.0, args.gate_ion, args.gate_closure)
     K = args.steps
-    tot = {p: torch.zeros((K, 4), dtype=torch.float64, device=dev) for p in ("fp64", "sur")}
+    fair_rtols = [float(r) for r in args.fair_rtols.split(",") if r.strip()]
+    loose = {f"fp64@{r:g}": r for r in fair_rtols}
+    paths = ["fp64", "sur"] + list(loose)
+    tot = {p: torch.zeros((K, 4), dtype=torch.float64, device=dev) for p in paths}
     fb = torch.zeros(K, dtype=torch.int32, device=dev)
     out_state, out_H, ms = {}, {}, {}
     # one coupling step of each path captured as a HIP graph (step + gas
@@ -370,8 +377,15 @@ def surrogate_main(args):
                                                    gate, aux, status, None, route_g, fb_g, V,
                                                    None, None, tot_g, cap),
     }
+    # the FP64 path at looser tolerances (the fair baseline of the surrogate)
+    loose_ctx = {}
+    for name, r in loose.items():
+        loose_ctx[name] = A.Context(ld_max, rtol=r, atol=W.atol_vector(r), variant=args.variant)
+        graphs[name] = A.adm1_graph_capture_step(loose_ctx[name].handle, X, wd.ld, T, feed,
+                                                 wd.dt, wd.n, aux, status, None, V, None, None,
+                                                 tot_g, cap)
     stream = torch.cuda.current_stream()
-    for path in ("fp64", "sur"):
+    for path in paths:
         X.copy_(X0); H.copy_(H0); hl.copy_(hl0); pos.copy_(pos0)
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -423,6 +437,23 @@ def surrogate_main(args):
     eph = ((ph_s - ph_f).abs() / ph_f).float()
     value = wd.n * K / (ms["sur"] / 1e3)
     v64 = wd.n * K / (ms["fp64"] / 1e3)
+    # looser FP64 tolerances against the rtol-1e-8 run: the loosest one that
+    # keeps tank methane flow (every step) and pH (p99) within 1e-3 is the
+    # fair baseline
+    sweep, fair = [], None
+    for name, r in sorted(loose.items(), key=lambda kv: -kv[1]):
+        c = tot[name][:, 2].cpu().numpy()
+        e_ch4 = float(np.max(np.abs(c - ch4[0]) / np.abs(ch4[0])))
+        e_ph = ((-torch.log10(out_H[name]) - ph_f).abs() / ph_f).float()
+        p99 = float(torch.quantile(e_ph[::max(1, wd.n >> 22)], 0.99))
+        row = {"rtol": r, "particle_steps_per_s": wd.n * K / (ms[name] / 1e3),
+               "tank_methane_rel_err_max": e_ch4, "ph_rel_err_p99": p99,
+               "ph_rel_err_max": float(e_ph.max())}
+        sweep.append(row)
+        if fair is None and e_ch4 <= 1e-3 and p99 <= 1e-3:
+            fair = row
+    for c in loose_ctx.values():
+        c.close()
     out = {
         "metric": "ADM1 particle-steps/sec (FP64 integrator vs gated surrogate) at stated error",
         "value": value,
@@ -444,6 +475,12 @@ def surrogate_main(args):
                      "kernel": "k_mlp_fwd (BF16 MFMA forward)", "avg_launch_ms": fwd_ms,
                      "flops_per_launch": mlp_flop},
         "detail": {"fp64_particle_steps_per_s": v64, "speedup_vs_fp64": value / v64,
+                   "fp64_rtol_sweep": sweep,
+                   "fair_baseline": None if fair is None else
+                   {"rtol": fair["rtol"], "particle_steps_per_s": fair["particle_steps_per_s"],
+                    "criteria": "loosest FP64 rtol with tank methane flow (every step) and "
+                                "pH (p99) within 1e-3 of the rtol-1e-8 run",
+                    "speedup_of_surrogate": value / fair["particle_steps_per_s"]},
                    "fallback_fraction": (fb.cpu().numpy() / wd.n).tolist(),
                    "tank_methane_rel_err": ch4_err,
                    "ph_rel_err_max": float(eph.max()),
