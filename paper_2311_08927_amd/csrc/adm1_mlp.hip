@@ -374,9 +374,15 @@ __global__ void k_splitk_sum(const float* part, int64_t stride, int S, int64_t c
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cnt) return;
-    float s = 0.f;
-    for (int z = 0; z < S; ++z) s += part[(int64_t)z * stride + i];
-    out[i] = s;
+    // four running sums (z mod 4), added in a fixed order: independent loads
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    int z = 0;
+    for (; z + 4 <= S; z += 4) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s[j] += part[(int64_t)(z + j) * stride + i];
+    }
+    for (; z < S; ++z) s[0] += part[(int64_t)z * stride + i];
+    out[i] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 // MSE loss on the 35 outputs: dY = 2 (Y - T) / (B 35) as FP32 [B][48], BF16

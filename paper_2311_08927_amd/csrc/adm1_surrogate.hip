@@ -673,7 +673,7 @@ int adm1_surrogate_train_step(adm1_surrogate* s, const uint16_t* X, const float*
     if (e == hipSuccess)
         e = mlp_loss(s->Yt, target, B, ldt, s->dY, s->dYb, s->dYT, s->lossp, loss, st);
     const int Bi = (int)B;
-    const int splitk = (int)std::min<int64_t>(kSplitMax, std::max<int64_t>(1, ldt / 512));
+    const int splitk = (int)std::min<int64_t>(kSplitMax, std::max<int64_t>(1, ldt / 256));
     // backward, last layer first; dZ of layer l is (dY, dYb, dYT) for l = 4
     for (int l = kMlpLayers - 1; l >= 0 && e == hipSuccess; --l) {
         const int I = kMlpPadIn[l], O = kMlpPadOut[l];
