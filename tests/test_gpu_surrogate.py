@@ -423,3 +423,27 @@ def test_output_bias_calibration_removes_mean_residual(torch_cuda):
     assert np.allclose(shift, -r0.mean(dim=0).cpu().numpy(), atol=1e-6)
     assert float(r1.mean(dim=0).abs().max()) < 1e-5
     assert torch.allclose(r1 - r1.mean(dim=0), r0 - r0.mean(dim=0), atol=1e-5)
+
+
+def test_featurize_wide_range_matches_oracle(torch_cuda):
+    """Features of states spread over 30 decades (below the floors, near 1,
+    up to 1e3) and random temperatures and feed flags equal the oracle's
+    BF16 values bit for bit (the logarithm is the kernel's own series)."""
+    torch = torch_cuda
+    from paper_2311_08927_amd import surrogate as S
+    n, ld = 3000, 3008
+    rng = np.random.default_rng(31)
+    X = np.zeros((35, ld))
+    X[:, :n] = np.exp(rng.uniform(np.log(1e-30), np.log(1e3), (35, n)))
+    X[:, :50] = 1.0 + rng.uniform(-1e-6, 1e-6, (35, 50))
+    T = rng.uniform(300.0, 320.0, ld)
+    D = np.where(rng.random(ld) < 0.3, 1.0, 0.0)
+    ctx, sur = make(ld)
+    norm = seeded_norm(4)
+    sur.set_weights(seeded_params(1), norm)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    got = sur.featurize(t(X), t(T), t(D), W.DT, n).cpu().numpy().view(np.uint16)
+    ref = M.bf16_bits(M.features(X[:, :n], T[:n], D[:n], W.DT, S.norm_dict(norm))
+                      .astype(np.float32))
+    assert np.all(got[:, 38:] == 0)
+    assert np.array_equal(got[:, :38], ref)
