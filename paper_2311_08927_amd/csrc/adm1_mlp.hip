@@ -272,10 +272,11 @@ __global__ void __launch_bounds__(kFwdThreads, 2) k_mlp_fwd(FwdArgs a)
 //   C[m][n] (+ z splitc) = sum_{k in chunk z} A[m lda + k] B[n ldb + k]
 // (BF16 in, FP32 out).  dW = H^T dZ reads the transposed activations and
 // gradients the forward and backward kernels save; dH = dZ W^T reads dZ
-// and W[in][out] as stored.  Each wave owns a 64 x 64 block of C (4 x 4
-// 16 x 16 tiles, 64 accumulator VGPRs) and loads its operand fragments
-// straight from memory (16 bytes per lane, the next k-step's issued before
-// the current one's matrix instructions); a block is 2 x 2 waves.  K is a
+// and W[in][out] as stored.  Each wave owns a (16 kTnRows) x 64 block of C
+// (kTnRows x 4 tiles of 16 x 16) and loads its operand fragments straight
+// from memory (16 bytes per lane, three k-steps in flight); a block is
+// 2 x 2 waves.  These products are small (~1 GFLOP), so the tile is sized
+// for enough waves to fill the chip rather than for maximal reuse.  K is a
 // multiple of 16: a remainder of 16 runs on the 16x16x16 instruction.
 // Rows and columns past M and N load the last valid ones and are not stored.
 // ---------------------------------------------------------------------------
@@ -289,38 +290,40 @@ struct TnArgs {
     int M, N, K, kchunk;
 };
 
+constexpr int kTnRows = 2;  // 16-row tiles per wave (a wave owns 16 kTnRows x 64 of C)
+
 __global__ void __launch_bounds__(256) k_gemm_tn(TnArgs g)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * 128 + (w & 1) * 64, n0 = blockIdx.x * 128 + (w >> 1) * 64;
+    const int m0 = blockIdx.y * (2 * 16 * kTnRows) + (w & 1) * (16 * kTnRows);
+    const int n0 = blockIdx.x * 128 + (w >> 1) * 64;
     if (m0 >= g.M || n0 >= g.N) return;  // no barriers below: a wave may leave
     const int kb = blockIdx.z * g.kchunk;
     const int ke = min(g.K, kb + g.kchunk);
     const int li = lane & 15, q = lane >> 4;
-    const uint16_t* ap[4];
+    const uint16_t* ap[kTnRows];
     const uint16_t* bp[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kTnRows; ++t)
         ap[t] = g.A + (int64_t)min(m0 + 16 * t + li, g.M - 1) * g.lda;
-        bp[t] = g.B + (int64_t)min(n0 + 16 * t + li, g.N - 1) * g.ldb;
-    }
-    f32x4 acc[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int t = 0; t < 4; ++t) bp[t] = g.B + (int64_t)min(n0 + 16 * t + li, g.N - 1) * g.ldb;
+    f32x4 acc[kTnRows][4];
+#pragma unroll
+    for (int r = 0; r < kTnRows; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kfull = kb + ((ke - kb) / 32) * 32;
     // three k-steps of fragments in flight (a ring of register buffers):
     // a step's loads are issued two steps before its matrix instructions
-    s16x8 fa[3][4], fb[3][4];
+    s16x8 fa[3][kTnRows], fb[3][4];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
         if (kb + 32 * j < kfull) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                fa[j][t] = *(const s16x8*)(ap[t] + kb + 32 * j + 8 * q);
-                fb[j][t] = *(const s16x8*)(bp[t] + kb + 32 * j + 8 * q);
-            }
+            for (int t = 0; t < kTnRows; ++t) fa[j][t] = *(const s16x8*)(ap[t] + kb + 32 * j + 8 * q);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) fb[j][t] = *(const s16x8*)(bp[t] + kb + 32 * j + 8 * q);
         }
     for (int k = kb; k < kfull; k += 96) {
 #pragma unroll
@@ -328,35 +331,34 @@ __global__ void __launch_bounds__(256) k_gemm_tn(TnArgs g)
             const int kj = k + 32 * j;
             if (kj < kfull) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int r = 0; r < kTnRows; ++r)
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
                         acc[r][c] = mfma32(fa[j][r], fb[j][c], acc[r][c]);
                 if (kj + 96 < kfull) {
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
+                    for (int t = 0; t < kTnRows; ++t)
                         fa[j][t] = *(const s16x8*)(ap[t] + kj + 96 + 8 * q);
-                        fb[j][t] = *(const s16x8*)(bp[t] + kj + 96 + 8 * q);
-                    }
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) fb[j][t] = *(const s16x8*)(bp[t] + kj + 96 + 8 * q);
                 }
             }
         }
     }
     if (kfull < ke) {  // 16 left
-        s16x4 a4[4], b4[4];
+        s16x4 a4[kTnRows], b4[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            a4[t] = *(const s16x4*)(ap[t] + kfull + 4 * q);
-            b4[t] = *(const s16x4*)(bp[t] + kfull + 4 * q);
-        }
+        for (int t = 0; t < kTnRows; ++t) a4[t] = *(const s16x4*)(ap[t] + kfull + 4 * q);
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int t = 0; t < 4; ++t) b4[t] = *(const s16x4*)(bp[t] + kfull + 4 * q);
+#pragma unroll
+        for (int r = 0; r < kTnRows; ++r)
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[r][c] = mfma16(a4[r], b4[c], acc[r][c]);
     }
     float* C = g.C + (int64_t)blockIdx.z * g.splitc;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < kTnRows; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int col = n0 + 16 * c + li;
@@ -652,7 +654,8 @@ hipError_t gemm_tn(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ld
         return hipErrorInvalidValue;
     TnArgs g;
     g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.M = M; g.N = N; g.K = K;
-    const dim3 tiles((unsigned)((N + 127) / 128), (unsigned)((M + 127) / 128));
+    const int bm = 2 * 16 * kTnRows;
+    const dim3 tiles((unsigned)((N + 127) / 128), (unsigned)((M + bm - 1) / bm));
     if (splitk <= 1) {
         g.C = C; g.ldc = ldc; g.splitc = 0; g.kchunk = K;
         hipLaunchKernelGGL(k_gemm_tn, dim3(tiles.x, tiles.y, 1), dim3(256), 0, s, g);
