@@ -215,6 +215,44 @@ def test_step_full_size_sampled(torch_cuda, orc, variant):
     assert worst <= PARITY_TOL
 
 
+def test_step_full_size_warm_sampled(torch_cuda, orc):
+    """The benchmark's configuration over three coupling intervals: 2^20
+    particles with warm starts carried between intervals (so the work queue
+    runs in cost order) and the pulsed feed zone; 96 sampled particles
+    recomputed by the oracle over the same three intervals with its own warm
+    starts, compared after the last one, step counts included."""
+    import torch
+    w = W.batched_population(1 << 20, seed=2)
+    ctx = make_ctx(w.ld)
+    dw = DeviceWorkload(w)
+    for k in range(3):
+        dw.set_D(w.D_at(k))
+        ctx.step(dw.X, dw.T, dw.D, dw.fidx, dw.S_in, w.dt, n=w.n, H=dw.H, hlast=dw.hlast,
+                 status=dw.status, nsteps=dw.nsteps)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(19)
+    idx = np.unique(np.concatenate([rng.choice(np.flatnonzero(w.zone), 16, replace=False),
+                                    rng.choice(w.n, 78, replace=False), [0, w.n - 1]]))
+    sub = W.subset(w, idx)
+    Xo = sub.X.copy()
+    Ho = np.full(sub.ld, -1.0)
+    hlo = np.full(sub.ld, -1.0)
+    for k in range(3):
+        st_o, cnt_o = orc.step(Xo, sub.T, w.D_at(k)[idx], sub.fidx, sub.feed, sub.dt, H=Ho,
+                               hlast=hlo, n=sub.n)
+        assert (st_o & 0x7F == 0).all()
+    it = torch.from_numpy(idx).cuda()
+    xg = dw.X[:, it].cpu().numpy()
+    worst = parity(xg, Xo, sub.n)
+    acc_g = dw.nsteps[0, it].cpu().numpy()
+    stg = dw.status.cpu().numpy()
+    print(f"full-size warm sampled parity {worst:.3e}; accepted steps in the third interval "
+          f"GPU {acc_g.sum()} oracle {cnt_o[0, :sub.n].sum()}")
+    assert (stg & 0x7F == 0).all()
+    assert worst <= PARITY_TOL
+    assert np.array_equal(acc_g, cnt_o[0, :sub.n])
+
+
 # ---------------------------------------------------------------------------
 # gas flux, determinism, edge cases
 # ---------------------------------------------------------------------------
