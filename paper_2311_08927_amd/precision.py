@@ -107,7 +107,7 @@ def main():
     print("| entry | rhs max | rhs p99 | state max | state p99 | state median |")
     print("|---|---|---|---|---|---|")
     for line in format_report(rep).splitlines()[1:]:
-        f = line.split()
+        f = ["—" if v == "nan" else v for v in line.split()]  # algebraic: no rhs row
         print("| " + " | ".join(f) + " |")
     per_step = [float(np.nanmax(np.array(s)[:, 0])) for s in rep["state"]]
     print("\nWorst state entry after each step: " + ", ".join(f"{v:.2e}" for v in per_step))
