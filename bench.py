@@ -64,7 +64,9 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed coupling steps (default 10 for the FP64 path, 96 for the "
+                         "surrogate)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=None,
                     help="particles (default 2^20 for the FP64 path, 2^24 for the surrogate)")
@@ -80,6 +82,18 @@ def parse():
                     help="surrogate: looser FP64 tolerances timed on the same field; the "
                          "loosest one within 1e-3 of the rtol-1e-8 run in tank methane flow "
                          "and pH (p99) is the fair baseline ('' to skip)")
+    ap.add_argument("--train-data", choices=["field", "batched"], default="field",
+                    help="surrogate: transitions to train on (field: a digester field of "
+                         "another seed, run as the coupling driver runs it; batched: the "
+                         "batched population)")
+    ap.add_argument("--gas-weight", type=float, default=1.0,
+                    help="surrogate: training-loss weight of the outputs that set the "
+                         "methane flow (S_ch4, S_IC and the three gas-phase states)")
+    ap.add_argument("--train-steps", type=int, default=96,
+                    help="surrogate: coupling steps of the training runs (the particle "
+                         "count is chosen for about 2^24 transitions)")
+    ap.add_argument("--train-seed", type=int, default=4,
+                    help="surrogate: seed of the initial weights and of the data split")
     ap.add_argument("--calibrate", type=int, default=1, choices=[0, 1],
                     help="surrogate: shift the output biases by the mean validation residual")
     ap.add_argument("--burn-in", type=int, default=2,
@@ -134,6 +148,8 @@ def main():
     args = parse()
     if args.n is None:
         args.n = (1 << 24) if args.path == "surrogate" else (1 << 20)
+    if args.steps is None:
+        args.steps = 96 if args.path == "surrogate" else 10
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
               "particle step shards by index range with no exchange besides four gas "
@@ -272,8 +288,10 @@ def main():
 
 def surrogate_main(args):
     """Gated surrogate against the FP64 path on the digester field: train the
-    network on integrator transitions of the batched population (2^20
-    particles x 16 coupling steps, particle split 90/5/5 with seed 4), then
+    network on integrator transitions of another digester field (seed 5; or
+    of the batched population with --train-data batched) over the same
+    horizon (96 coupling steps x 174,784 particles, about 2^24 transitions,
+    particle split 90/5/5 with seed 4), then
     run the same coupling steps (feed mask, step, gas flux, advection) of the
     field through both paths from the same burned-in states."""
     import torch
@@ -286,7 +304,7 @@ def surrogate_main(args):
     torch.cuda.set_device(dev)
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     wd = W.digester_field(args.n, seed=3, steps=args.burn_in + args.steps)
-    n_train = 1 << 20
+    n_train = W.pad_ld(((1 << 24) + args.train_steps - 1) // args.train_steps, 64)
     ld_max = max(wd.ld, W.pad_ld(n_train, 64))
     ctx = A.Context(ld_max, rtol=args.rtol, atol=W.atol_vector(args.rtol), variant=args.variant)
     # the surrogate's own context: its fallback integrations run at
@@ -298,15 +316,21 @@ def surrogate_main(args):
     floor = S.default_floor()
     # --- training data and training (untimed) --------------------------------
     t0 = time.perf_counter()
-    wt = W.batched_population(n_train, seed=2, steps=16)
-    sur.set_weights(S.init_params(4), S.identity_norm(floor))
-    states, Ds, ok, T = S.integrate_states(ctx, wt, 16)
-    g = np.random.default_rng(4)
+    sur.set_weights(S.init_params(args.train_seed), S.identity_norm(floor))
+    if args.train_data == "field":
+        wt = W.digester_field(n_train, seed=5, steps=args.train_steps)
+        states, Ds, ok, T = S.integrate_field_states(ctx, wt, args.train_steps)
+    else:
+        wt = W.batched_population(n_train, seed=2, steps=args.train_steps)
+        states, Ds, ok, T = S.integrate_states(ctx, wt, args.train_steps)
+    g = np.random.default_rng(args.train_seed)
     perm = g.permutation(wt.n)
     tr = torch.from_numpy(np.sort(perm[: int(0.9 * wt.n)])).to(dev)
     va = torch.from_numpy(np.sort(perm[int(0.9 * wt.n): int(0.95 * wt.n)])).to(dev)
-    norm = S.fit_norm(sur, states, Ds, T, wt.dt, wt.n, floor, rows=tr)
-    sur.set_weights(S.init_params(4), norm)
+    out_weight = np.ones(35)
+    out_weight[[8, 9, 32, 33, 34]] = args.gas_weight
+    norm = S.fit_norm(sur, states, Ds, T, wt.dt, wt.n, floor, rows=tr, out_weight=out_weight)
+    sur.set_weights(S.init_params(args.train_seed), norm)
     X, Tg = S.dataset(sur, states, Ds, T, wt.dt, wt.n, rows=tr)
     keep = ok[:, tr].reshape(-1)
     X, Tg = X[keep].contiguous(), Tg[keep].contiguous()
@@ -443,6 +467,15 @@ def surrogate_main(args):
     ph_f = -torch.log10(out_H["fp64"])
     ph_s = -torch.log10(out_H["sur"])
     eph = ((ph_s - ph_f).abs() / ph_f).float()
+    # per-state error of the surrogate path's final states against the FP64
+    # path's (every 64th particle; scale floor 1e-4 x the nominal entry)
+    sub = slice(0, wd.n, 64)
+    rel = ((out_state["sur"][:, sub] - out_state["fp64"][:, sub]).abs() /
+           torch.maximum(out_state["fp64"][:, sub].abs(), 1e-4 * nom)).float()
+    state_err = {"median": torch.quantile(rel, 0.5, dim=1).tolist(),
+                 "p99": torch.quantile(rel, 0.99, dim=1).tolist(),
+                 "mean_signed": ((out_state["sur"][:, sub] - out_state["fp64"][:, sub]).sum(1) /
+                                 out_state["fp64"][:, sub].abs().sum(1)).tolist()}
     value = wd.n * K / (ms["sur"] / 1e3)
     v64 = wd.n * K / (ms["fp64"] / 1e3)
     # looser FP64 tolerances against the rtol-1e-8 run: the loosest one that
@@ -493,12 +526,14 @@ def surrogate_main(args):
                    "fallback_fraction": (fb.cpu().numpy() / wd.n).tolist(),
                    "tank_methane_rel_err": ch4_err,
                    "ph_rel_err_max": float(eph.max()),
+                   "final_state_rel_err": state_err,
                    "audit": {"sample": "4096 seeded particles per step; accepted ones "
                                        "integrated exactly from their pre-step states",
                              "accepted": audit_n, "rel_err_max": audit_max,
                              "rel_err_p99": audit_p99},
                    "ph_rel_err_p99": float(torch.quantile(eph[::max(1, wd.n >> 22)], 0.99)),
-                   "train": {"transitions": int(keep.sum()), "epochs": args.train_epochs,
+                   "train": {"data": args.train_data,
+                             "transitions": int(keep.sum()), "epochs": args.train_epochs,
                              "steps": n_train_steps, "seconds": train_s,
                              "data_seconds": gen_s, "loss_first_last": [hist[0], hist[-1]],
                              "val_mse": val_mse,

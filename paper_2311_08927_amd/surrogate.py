@@ -277,6 +277,36 @@ def integrate_states(ctx, w: W.Workload, steps: int):
     return states, Ds, torch.stack(ok), T
 
 
+def integrate_field_states(ctx, w: W.Workload, steps: int):
+    """Advance a digester field w (workloads.digester_field) with the FP64
+    integrator for `steps` coupling intervals, as the coupling driver does:
+    feed mask from the positions, step, advection by the seeded flow.
+    Returns what integrate_states returns."""
+    import torch
+    from . import adm1 as A
+    dev = "cuda"
+    X = torch.from_numpy(np.ascontiguousarray(w.X)).to(dev)
+    T = torch.from_numpy(w.T).to(dev)
+    S_in = torch.from_numpy(w.feed).to(dev)
+    pos = torch.from_numpy(np.ascontiguousarray(w.extra["pos"])).to(dev)
+    flow = A.make_flow(w.extra["flow"])
+    H = torch.full((w.n,), -1.0, dtype=torch.float64, device=dev)
+    hl = torch.full((w.n,), -1.0, dtype=torch.float64, device=dev)
+    status = torch.empty(w.n, dtype=torch.uint8, device=dev)
+    fidx = torch.empty(w.n, dtype=torch.int32, device=dev)
+    dt_s = w.dt * 86400.0
+    states, Ds, ok = [X.clone()], [], []
+    for s in range(steps):
+        D = torch.empty(w.n, dtype=torch.float64, device=dev)
+        A.adm1_feed_mask(pos, w.ld, w.n, W.INLET_Z, W.INLET_R, 1.0, 1, 0, D, fidx)
+        ctx.step(X, T, D, fidx, S_in, w.dt, n=w.n, H=H, hlast=hl, status=status)
+        A.adm1_advect(pos, w.ld, w.n, flow, dt_s, int(dt_s))
+        states.append(X.clone())
+        Ds.append(D)
+        ok.append(status == 0)
+    return states, Ds, torch.stack(ok), T
+
+
 def dataset(sur: "Surrogate", states, Ds, T, dt, n, rows=None):
     """Features and targets (kernel outputs under the surrogate's current
     normalisation) of every transition, stacked step by step; `rows`
@@ -294,10 +324,13 @@ def dataset(sur: "Surrogate", states, Ds, T, dt, n, rows=None):
     return torch.cat(feats), torch.cat(targs)
 
 
-def fit_norm(sur: "Surrogate", states, Ds, T, dt, n, floor, rows=None) -> adm1_mlp_norm:
+def fit_norm(sur: "Surrogate", states, Ds, T, dt, n, floor, rows=None,
+             out_weight=None) -> adm1_mlp_norm:
     """Normalisation from the raw (identity-normalised) features and targets
     of the training transitions: per-column mean and spread; columns without
-    spread keep unit scale."""
+    spread keep unit scale.  out_weight (optional, per output) divides an
+    output's spread by its square root, which weights that output's share of
+    the mean-squared training loss by out_weight."""
     params, _ = sur.get_weights()
     sur.set_weights(params, identity_norm(floor))
     Xr, Tr = dataset(sur, states, Ds, T, dt, n, rows)
@@ -308,6 +341,8 @@ def fit_norm(sur: "Surrogate", states, Ds, T, dt, n, floor, rows=None) -> adm1_m
     out_mean = Tr.mean(0).double().cpu().numpy()
     out_sd = Tr.std(0).double().cpu().numpy()
     out_sd = np.where(out_sd > 1e-8, out_sd, 1.0)
+    if out_weight is not None:
+        out_sd = out_sd / np.sqrt(np.asarray(out_weight, dtype=np.float64))
     return make_norm(in_mean, in_sd, out_mean, out_sd, floor)
 
 
