@@ -11,6 +11,8 @@ oracle); callers add an oracle sample where they can afford one.
 """
 from __future__ import annotations
 
+import sys
+
 import numpy as np
 
 from . import workloads as W
@@ -75,7 +77,7 @@ def main():
     from . import adm1 as A
     ap = argparse.ArgumentParser(description=main.__doc__)
     ap.add_argument("--n", type=int, default=1 << 22)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=96)
     ap.add_argument("--rtol", type=float, default=1e-8)
     args = ap.parse_args()
     w = W.digester_field(args.n, seed=3, steps=args.steps)
@@ -96,6 +98,7 @@ def main():
         if s > 0:
             A.adm1_advect(pos, w.ld, w.n, flow, dt_s, int(dt_s))
         mask()
+        print(f"# step {s}", file=sys.stderr, flush=True)
         return D
 
     mask()
