@@ -209,10 +209,14 @@ class Oracle:
         return C, N
 
     def fixed(self, x, T, D, s_in, dt, nsteps, method="rk4"):
+        """nsteps equal steps of `method` over dt: "rk4", "rodas4" (no step
+        control) or "euler" (the explicit update of the paper's fixed-step
+        scheme, sec. 2.3 and 4.3); then the algebraic write-back."""
         x = np.array(x, dtype=np.float64)
         s_in = np.ascontiguousarray(s_in, dtype=np.float64)
+        code = {"rk4": 0, "rodas4": 1, "euler": 2}[method]
         rc = lib().orc_fixed(ctypes.byref(self._p), ctypes.byref(self._o), _dp(x), T, D,
-                             _dp(s_in), dt, nsteps, 0 if method == "rk4" else 1)
+                             _dp(s_in), dt, nsteps, code)
         if rc != 0:
             raise RuntimeError("fixed-step integration failed")
         return x

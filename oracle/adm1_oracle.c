@@ -1023,8 +1023,12 @@ void orc_gas_flux(const orc_params *p, const double *x, double T, double V_liq,
     q4[3] = q * creal(r.p_co2) / P;
 }
 
-/* Fixed-step integrators for the accuracy pins: classical RK4 and Rodas4
- * without step control, nsteps equal steps over dt. */
+/* Fixed-step integrators, nsteps equal steps over dt: classical RK4 and
+ * Rodas4 without step control (the accuracy pins), and the explicit Euler
+ * update y <- y + h f(y) of the paper's fixed-step scheme (sec. 2.3: small
+ * synchronised steps need no step-size control; sec. 4.3: Dt = 0.5 s as ten
+ * internal steps), method 2.  Every evaluation of f solves eqs. 7 and 8 at
+ * the current differential state.  A non-finite state after a step fails. */
 int orc_fixed(const orc_params *p, const orc_opts *o, double *x, double T, double D,
               const double *s_in, double dt, int nsteps, int method)
 {
@@ -1038,7 +1042,12 @@ int orc_fixed(const orc_params *p, const orc_opts *o, double *x, double T, doubl
     double y[ND], h = dt / nsteps;
     for (int k = 0; k < ND; k++) y[k] = x[DIFF[k]];
     for (int s = 0; s < nsteps; s++) {
-        if (method == 0) {
+        if (method == 2) {
+            double f[ND];
+            if (rhs_real(&m, y, f)) return -1;
+            for (int i = 0; i < ND; i++) y[i] += h * f[i];
+            if (!finite_all(y, ND)) return -1;
+        } else if (method == 0) {
             double k1[ND], k2[ND], k3[ND], k4[ND], a[ND];
             if (rhs_real(&m, y, k1)) return -1;
             for (int i = 0; i < ND; i++) a[i] = y[i] + 0.5 * h * k1[i];

@@ -519,3 +519,64 @@ def test_failed_particle_keeps_input():
     st, _ = o.step(X, [T, T], [D, D], [0, 0], feed[None, :], DT, nthreads=1)
     assert st[1] == 4 and st[0] & 0x7F == 0
     assert np.isnan(X[3, 1]) and np.array_equal(X[[0, 1, 2], 1], x[[0, 1, 2]])
+
+
+# ---------------------------------------------------------------------------
+# Fixed-step explicit scheme of the paper (sec. 2.3, sec. 4.3)
+# ---------------------------------------------------------------------------
+SEC = 1.0 / 86400.0  # one second in days
+
+
+def test_euler_washout_recursion():
+    """No kinetics, no gas exchange: explicit Euler on x' = D (x_in - x) is
+    the recursion x_n = x_in + (1 - D h)^n (x_0 - x_in) in every liquid
+    entry (S_h2 is algebraic)."""
+    v = values()
+    for k in list(v):
+        if k.startswith(("k_m_", "k_dec_", "k_hyd_")) or k in ("k_dis",):
+            v[k] = 0.0
+    v.update(k_L_a=0.0, k_p_per_V_liq=0.0)
+    o = Oracle(v, rtol=1e-8)
+    x, feed, _, T = perturbed(3)
+    D, dt, n = 40.0, 0.01, 7
+    xe = o.fixed(x, T, D, feed, dt, n, "euler")
+    h = dt / n
+    liq = [i for i in range(NLIQ) if i != IX["S_h2"]]
+    ref = feed[liq] + (1.0 - D * h) ** n * (x[liq] - feed[liq])
+    assert np.max(np.abs(xe[liq] - ref) / np.abs(ref)) < 1e-13
+    assert np.array_equal(xe[32:35], x[32:35])
+
+
+def test_euler_first_order():
+    """Global error of explicit Euler against the RK4 reference halves with
+    the step (order 1), over a quarter of a coupling interval."""
+    x, feed, D, T = perturbed_smooth(5)
+    o = closed_valve(1e-8)
+    dt = DT / 4
+    ref = _rk4_richardson(o, x, T, D, feed, dt)
+    errs = []
+    for n in [256, 512, 1024]:
+        y = o.fixed(x, T, D, feed, dt, n, "euler")
+        errs.append(np.max(np.abs(y[DIFF] - ref[DIFF]) / np.maximum(np.abs(ref[DIFF]), 1e-3)))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(0.85 < p < 1.15 for p in orders), (errs, orders)
+
+
+@pytest.mark.parametrize("seed", [2, 9])
+def test_euler_paper_interval_against_adaptive(seed):
+    """The paper's coupling interval Dt = 0.5 s in ten explicit steps of
+    0.05 s against the adaptive Rodas4 solution at rtol 1e-10: the
+    difference is the explicit scheme's own truncation error (largest in the
+    headspace CO2, which relaxes at ~1,600 1/d from a perturbed state), a
+    few 1e-6, and it falls tenfold with ten times the steps."""
+    x, feed, D, T = perturbed(seed)
+    nom = nominal()[0]
+    o = Oracle(PARAMS, rtol=1e-10, atol=1e-4 * 1e-10 * nom[DIFF])
+    Dt = 0.5 * SEC
+    ya = _run(o, x, T, D, feed, Dt)
+    err = []
+    for n in (10, 100):
+        ye = o.fixed(x, T, D, feed, Dt, n, "euler")
+        err.append((np.abs(ye - ya) / np.maximum(np.abs(ya), 1e-4 * nom)).max())
+    assert err[0] < 2e-5
+    assert 8.0 < err[0] / err[1] < 12.0, err
