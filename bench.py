@@ -70,7 +70,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=None,
                     help="particles (default 2^20 for the FP64 path, 2^24 for the surrogate)")
-    ap.add_argument("--path", choices=["fp64", "surrogate"], default="fp64")
+    ap.add_argument("--path", choices=["fp64", "surrogate", "fixed"], default="fp64",
+                    help="fp64: adaptive Rodas4 step (default); surrogate: gated MLP against "
+                         "it; fixed: the paper's fixed-step explicit scheme")
+    ap.add_argument("--method", choices=["euler", "rk4"], default="euler",
+                    help="fixed path: explicit update")
+    ap.add_argument("--interval-s", type=float, default=0.5,
+                    help="fixed path: coupling interval in seconds (the paper's Dt)")
+    ap.add_argument("--substeps", type=int, default=10,
+                    help="fixed path: explicit steps per interval (the paper's ten)")
     ap.add_argument("--train-epochs", type=int, default=24)
     ap.add_argument("--gate-ion", type=float, default=1e-2,
                     help="surrogate gate: tolerance of the proposed ions and S_h2")
@@ -147,9 +155,9 @@ def cpu_baseline(w, rtol, n_sample, steps):
 def main():
     args = parse()
     if args.n is None:
-        args.n = (1 << 24) if args.path == "surrogate" else (1 << 20)
+        args.n = {"surrogate": 1 << 24, "fixed": 110_929}.get(args.path, 1 << 20)
     if args.steps is None:
-        args.steps = 96 if args.path == "surrogate" else 10
+        args.steps = {"surrogate": 96, "fixed": 100}.get(args.path, 10)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
               "particle step shards by index range with no exchange besides four gas "
@@ -163,6 +171,8 @@ def main():
     from paper_2311_08927_amd import workloads as W
     if args.path == "surrogate":
         return surrogate_main(args)
+    if args.path == "fixed":
+        return fixed_main(args)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -282,6 +292,115 @@ def main():
     }
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.rtol, args.cpu_sample, args.cpu_steps)
+        out["detail"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out))
+
+
+def fixed_cpu_baseline(w, dt, substeps, method, n_sample, steps):
+    """The oracle's fixed-step integrator, as it stands (one particle per
+    call, one thread), on a seeded sample of the same population."""
+    from oracle.adm1 import Oracle
+    from paper_2311_08927_amd import workloads as W
+    orc = Oracle(W.params_path(), rtol=1e-8, atol=W.atol_vector(1e-8))
+    idx = np.sort(np.random.default_rng(123).choice(w.n, min(n_sample, w.n), replace=False))
+    X = w.X[:, idx].copy()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for j, i in enumerate(idx):
+            X[:, j] = orc.fixed(X[:, j], w.T[i], w.D[i], w.feed[w.fidx[i]], dt, substeps,
+                                method)
+    el = time.perf_counter() - t0
+    return {"value": len(idx) * steps / el, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{len(idx)} particles x {steps} coupling intervals of the same "
+                      f"population, one particle per call on one thread, {el:.1f} s"}
+
+
+def fixed_main(args):
+    """The paper's own fixed-step scheme (sec. 2.3: synchronised coupling steps
+    small enough that no step control is needed; sec. 4.3: 110,929 particles
+    of the CSTR case, Dt = 0.5 s in ten internal steps).  A step of the metric
+    is one coupling interval of one particle; HIP events bracket every launch
+    on the launching stream."""
+    import torch
+
+    from paper_2311_08927_amd import adm1 as A
+    from paper_2311_08927_amd import flops as F
+    from paper_2311_08927_amd import workloads as W
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = W.cstr_population(args.n, seed=1)
+    dt = args.interval_s / 86400.0
+    meth = A.FIXED_EULER if args.method == "euler" else A.FIXED_RK4
+    ctx = A.Context(w.ld, rtol=1e-8, atol=W.atol_vector(1e-8),
+                    rate_precision=args.rate_precision)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    X0 = t(w.X)
+    X = X0.clone()
+    T, D, fidx, S_in = t(w.T), t(w.D), t(w.fidx), t(w.feed)
+    H = torch.full((w.n,), -1.0, dtype=torch.float64, device=dev)
+    status = torch.zeros(w.n, dtype=torch.uint8, device=dev)
+    K = args.steps
+    newton = torch.zeros((K, w.n), dtype=torch.int32, device=dev)
+    feed = A.feed_struct(D, fidx, S_in)
+    stream = torch.cuda.current_stream()
+
+    def one(k):
+        A.adm1_step_fixed(ctx.handle, X, w.ld, T, feed, dt, args.substeps, meth, w.n, H,
+                          status, newton[k], stream)
+
+    for k in range(args.warmup):
+        one(0)
+    torch.cuda.synchronize()
+    X.copy_(X0)
+    H.fill_(-1.0)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for k in range(K):
+        ev[k][0].record(stream)
+        one(k)
+        ev[k][1].record(stream)
+    end.record(stream)
+    end.synchronize()
+    print(f"# {K} intervals done", file=sys.stderr, flush=True)
+    total_ms = start.elapsed_time(end)
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    newt = int(newton.sum().item())
+    flop = F.fixed_flops(args.method, args.substeps, newt, w.n * K)
+    achieved = flop / (sum(launch_ms) / 1e3)
+    value = w.n * K / (total_ms / 1e3)
+    st = status.cpu().numpy()
+    out = {
+        "metric": "ADM1 particle-steps/sec (FP64 integrator vs gated surrogate) at stated error",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": total_ms / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.rate_precision == 0 else "f64 (rates f32)",
+        "data": "synthetic",
+        "config": {"workload": f"CSTR population of the paper's parallel benchmark shape: "
+                               f"{w.n} particles, coupling interval {args.interval_s:g} s "
+                               f"in {args.substeps} explicit {args.method} steps, "
+                               f"{K} intervals",
+                   "path": "fixed-step explicit scheme", "method": args.method,
+                   "substeps": args.substeps, "interval_s": args.interval_s},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "kernel": f"k_fixed ({args.method})",
+                     "avg_launch_ms": sum(launch_ms) / K, "flops_per_launch": flop / K},
+        "detail": {"substeps_per_s": value * args.substeps,
+                   "newton_per_particle_interval": newt / (w.n * K),
+                   "status_counts": np.bincount(st & 0x7F, minlength=5).tolist(),
+                   "hbm_bytes_per_particle_step": F.BYTES_FIXED,
+                   "hbm_frac": w.n * F.BYTES_FIXED / (sum(launch_ms) / K / 1e3) / PEAK_HBM},
+    }
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = fixed_cpu_baseline(w, dt, args.substeps, args.method,
+                                                 args.cpu_sample, args.cpu_steps)
         out["detail"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
     print(json.dumps(out))
 

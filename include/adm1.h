@@ -171,6 +171,28 @@ int adm1_step_particles(adm1_ctx *ctx, double *state, int64_t ld, const double *
                         const adm1_feed *feed, double dt_days, int64_t n, adm1_aux *aux,
                         uint8_t *status, int32_t *nsteps, void *stream);
 
+/* The paper's own fixed-step scheme (sec. 2.3: coupling steps small enough
+ * that no step-size control is needed; sec. 4.3: Dt = 0.5 s in ten internal
+ * steps of 0.05 s).  Advances particles 0..n-1 by dt_days IN PLACE in
+ * `substeps` equal explicit steps (1..2^20): method ADM1_FIXED_EULER
+ * (y <- y + h f(y)) or ADM1_FIXED_RK4 (classical fourth order); every
+ * evaluation of f solves S_H+ and S_h2 from eqs. 7-8 at the current state,
+ * warm-started from the previous roots, and the algebraic entries are
+ * written back at the end.  The rates use opts.rate_precision.  state, ld,
+ * temp_K, feed as in adm1_step_particles; H (nullable, [n]): S_H+ warm start
+ * in (<= 0: cold), root out; status: [n] uint8, 0 ok, 1 an algebraic solve
+ * failed, 2 a step produced a non-finite state (the step is too long for
+ * the explicit scheme), 4 non-finite or invalid input, bit 0x80 a negative
+ * differential entry; a failed particle keeps its input.  newton (nullable,
+ * [n] int32): algebraic Newton iterations per particle.  Asynchronous on
+ * `stream`; no allocation.  Invalid arguments: ADM1_E_NULL, ADM1_E_SIZE,
+ * ADM1_E_DT (dt_days not positive and finite), ADM1_E_OPTS (substeps or
+ * method out of range), ADM1_E_FEED, ADM1_E_NOT_DEVICE. */
+enum { ADM1_FIXED_EULER = 0, ADM1_FIXED_RK4 = 1 };
+int adm1_step_fixed(adm1_ctx *ctx, double *state, int64_t ld, const double *temp_K,
+                    const adm1_feed *feed, double dt_days, int32_t substeps, int32_t method,
+                    int64_t n, double *H, uint8_t *status, int32_t *newton, void *stream);
+
 /* Headspace gas flows (sec. 1: release of gaseous components) of particles
  * 0..n-1: q_gas = V_liq k_p max(0, P_gas - P_atm) P_gas / P_atm and
  * q_ch4 = q_gas p_ch4 / P_gas (m3/d), with P_gas the sum of the partial

@@ -66,6 +66,8 @@ def lib():
         L.adm1_destroy.argtypes = [vp]
         L.adm1_step_particles.restype = ctypes.c_int
         L.adm1_step_particles.argtypes = [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp]
+        L.adm1_step_fixed.restype = ctypes.c_int
+        L.adm1_step_fixed.argtypes = [vp, vp, i64, vp, vp, dbl, i32, i32, i64, vp, vp, vp, vp]
         L.adm1_gas_flux.restype = ctypes.c_int
         L.adm1_gas_flux.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, vp, vp]
         L.adm1_rhs.restype = ctypes.c_int
@@ -175,6 +177,19 @@ def adm1_step_particles(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, n, aux
                                    _ptr(nsteps), _stream(stream))
     if check:
         _check(rc, "adm1_step_particles")
+    return rc
+
+
+FIXED_EULER, FIXED_RK4 = 0, 1
+
+
+def adm1_step_fixed(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, substeps, method, n,
+                    H=None, status=None, newton=None, stream=None, check=True) -> int:
+    rc = lib().adm1_step_fixed(ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed),
+                               float(dt_days), int(substeps), int(method), int(n), _ptr(H),
+                               _ptr(status), _ptr(newton), _stream(stream))
+    if check:
+        _check(rc, "adm1_step_fixed")
     return rc
 
 
@@ -310,6 +325,17 @@ class Context:
         aux = None if H is None and hlast is None else adm1_aux(_ptr(H), _ptr(hlast))
         adm1_step_particles(self.handle, state, state.shape[1], T, feed, dt, n, aux, status,
                             nsteps, stream)
+        return status
+
+    def step_fixed(self, state, T, D, fidx, S_in, dt, substeps, method=FIXED_EULER, n=None,
+                   H=None, status=None, newton=None, stream=None):
+        """The fixed-step explicit scheme (adm1_step_fixed) in place."""
+        import torch
+        n = state.shape[1] if n is None else n
+        if status is None:
+            status = torch.empty(n, dtype=torch.uint8, device=state.device)
+        adm1_step_fixed(self.handle, state, state.shape[1], T, feed_struct(D, fidx, S_in), dt,
+                        substeps, method, n, H, status, newton, stream)
         return status
 
     def rhs(self, state, T, D, fidx, S_in, n=None, rate_precision=0, stream=None):

@@ -9,6 +9,7 @@
 
 #include "adm1.h"
 #include "adm1_ctx.h"
+#include "adm1_fixed.h"
 #include "adm1_kernels.h"
 
 using adm1::DevParams;
@@ -392,6 +393,30 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
     default:
         return ADM1_E_VARIANT;
     }
+}
+
+int adm1_step_fixed(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,
+                    const adm1_feed* feed, double dt_days, int32_t substeps, int32_t method,
+                    int64_t n, double* H, uint8_t* status, int32_t* newton, void* stream)
+{
+    if (!ctx || !state || !temp_K || !status) return ADM1_E_NULL;
+    int rc = check_layout(ctx, ld, n);
+    if (rc) return rc;
+    if (!(dt_days > 0.0) || !std::isfinite(dt_days)) return ADM1_E_DT;
+    if (substeps < 1 || substeps > (1 << 20)) return ADM1_E_OPTS;
+    if (method != ADM1_FIXED_EULER && method != ADM1_FIXED_RK4) return ADM1_E_OPTS;
+    rc = check_feed(feed);
+    if (rc) return rc;
+    if (!is_device(state) || !is_device(temp_K) || !is_device(status)) return ADM1_E_NOT_DEVICE;
+    if ((H && !is_device(H)) || (newton && !is_device(newton))) return ADM1_E_NOT_DEVICE;
+    if (n == 0) return ADM1_OK;
+    adm1::FixedArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.p = ctx->dp;
+    a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.D = feed->D; a.fidx = feed->idx;
+    a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.dt = dt_days; a.substeps = substeps;
+    a.method = method; a.H = H; a.status = status; a.newton = newton;
+    return hip_rc(adm1::launch_fixed(a, ctx->opts.rate_precision, (hipStream_t)stream));
 }
 
 int adm1_set_order(adm1_ctx* ctx, int32_t mode)

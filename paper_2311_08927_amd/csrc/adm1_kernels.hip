@@ -6,10 +6,12 @@
 // Newton matrix of the 28 differential entries plus the two constraints.
 //
 // This file holds the one-lane-per-particle kernels (step with a dense
-// bordered LU, right-hand side, Jacobian, gas flux).  The two-lanes-per-
-// particle register-resident step lives in adm1_step_sparse2.hip.
+// bordered LU, the paper's fixed-step explicit scheme, right-hand side,
+// Jacobian, gas flux).  The two-lanes-per-particle register-resident step
+// lives in adm1_step_sparse2.hip.
 #include <hip/hip_runtime.h>
 
+#include "adm1_fixed.h"
 #include "adm1_kernels.h"
 #include "adm1_model.h"
 #include "adm1_rodas4.h"
@@ -291,6 +293,86 @@ __global__ void __launch_bounds__(64, 1) k_step1(StepArgs a)
     }
 }
 
+// The paper's fixed-step scheme: `substeps` equal explicit steps over the
+// interval, explicit Euler (M = 0) or classical RK4 (M = 1), every
+// right-hand-side evaluation solving eqs. 7-8 at the current differential
+// state (warm-started from the previous roots); then the algebraic
+// write-back.  Status: 0 ok, 1 an algebraic solve failed, 2 a step produced a
+// non-finite state, 4 non-finite or invalid input; bit 0x80 flags a negative
+// differential entry.  A failed particle keeps its input.
+template <typename R, int M>
+__global__ void __launch_bounds__(64) k_fixed(FixedArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const DevParams& p = a.p;
+    double y[NY];
+    for (int k = 0; k < NY; ++k) y[k] = a.state[state_row(k) * a.ld + i];
+    const double T = a.T[i], D = a.D[i];
+    const int fi = a.fidx[i];
+    double H = a.H ? a.H[i] : -1.0;
+    double Sh2 = a.state[ROW_SH2 * a.ld + i];
+    int it = 0, st = 0;
+    const double* sin = nullptr;
+    if (!all_finite(y, NY) || !isfinite(T) || !isfinite(D) || !(T > 0.0) || fi < 0 ||
+        fi >= a.n_feed) {
+        st = 4;
+    } else {
+        sin = a.S_in + (int64_t)fi * NLIQ;
+        for (int k = 0; k < NLIQ; ++k)
+            if (!isfinite(sin[k])) st = 4;
+    }
+    if (st == 0) {
+        const TConst c = tconst(p, T);
+        const double h = a.dt / a.substeps;
+        double f[NY];
+        for (int s = 0; s < a.substeps && st == 0; ++s) {
+            if (M == 0) {
+                if (rhs<R>(p, c, y, D, sin, H, Sh2, f, it)) {
+                    st = 1;
+                    break;
+                }
+                for (int k = 0; k < NY; ++k) y[k] = fma(h, f[k], y[k]);
+            } else {
+                double y0[NY], acc[NY];
+                for (int k = 0; k < NY; ++k) y0[k] = y[k];
+                // stages 1-3: f at the stage argument, then the next argument
+                const double wt[3] = {1.0, 2.0, 2.0};
+                const double ah[3] = {0.5 * h, 0.5 * h, h};
+                for (int q = 0; q < 3 && st == 0; ++q) {
+                    if (rhs<R>(p, c, y, D, sin, H, Sh2, f, it)) {
+                        st = 1;
+                        break;
+                    }
+                    for (int k = 0; k < NY; ++k) {
+                        acc[k] = q ? fma(wt[q], f[k], acc[k]) : f[k];
+                        y[k] = fma(ah[q], f[k], y0[k]);
+                    }
+                }
+                if (st) break;
+                if (rhs<R>(p, c, y, D, sin, H, Sh2, f, it)) {
+                    st = 1;
+                    break;
+                }
+                for (int k = 0; k < NY; ++k) y[k] = fma(h / 6.0, acc[k] + f[k], y0[k]);
+            }
+            if (!all_finite(y, NY)) st = 2;
+        }
+        // algebraic write-back: S_H+ and S_h2 at the final differential state
+        if (st == 0 &&
+            rhs_in<R>(p, c, y, D, FeedInflow{D, sin}, H, Sh2, [](int, double) {}, it, true))
+            st = 1;
+        if (st == 0) {
+            store_state(p, c, a.state, a.ld, i, y, H, Sh2);
+            if (a.H) a.H[i] = H;
+            for (int k = 0; k < NY; ++k)
+                if (y[k] < 0.0) st |= 0x80;
+        }
+    }
+    a.status[i] = (uint8_t)st;
+    if (a.newton) a.newton[i] = it;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(64) k_rhs(RhsArgs a)
 {
@@ -429,6 +511,24 @@ hipError_t launch_step1(const StepArgs& a, int rate_precision, bool sparse, hipS
             hipLaunchKernelGGL((k_step1<float, LinDense>), dim3(grid), dim3(64), 0, s, a);
         else
             hipLaunchKernelGGL((k_step1<double, LinDense>), dim3(grid), dim3(64), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fixed(const FixedArgs& a, int rate_precision, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((a.n + 63) / 64);
+    if (grid == 0) return hipSuccess;
+    if (a.method == 0) {
+        if (rate_precision)
+            hipLaunchKernelGGL((k_fixed<float, 0>), dim3(grid), dim3(64), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_fixed<double, 0>), dim3(grid), dim3(64), 0, s, a);
+    } else {
+        if (rate_precision)
+            hipLaunchKernelGGL((k_fixed<float, 1>), dim3(grid), dim3(64), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_fixed<double, 1>), dim3(grid), dim3(64), 0, s, a);
     }
     return hipGetLastError();
 }

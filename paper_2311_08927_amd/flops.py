@@ -54,3 +54,28 @@ def total_flops(attempts: int, newton: int, particles: int) -> float:
     Each interval also evaluates the right-hand side at its start and end."""
     return float(attempts) * per_attempt() + float(newton) * F_NEWTON + \
         particles * (F_TCONST + 2 * F_RHS_BASE)
+
+
+# --- the fixed-step explicit scheme (sec. 2.3, sec. 4.3) --------------------
+# explicit Euler update y + h f (one fused multiply-add per entry)
+F_EULER_VECTOR = 2 * 28
+# classical RK4: three stage arguments and the weighted sum (13 flops per
+# entry as the kernel forms them)
+F_RK4_VECTOR = 13 * 28
+# the algebraic write-back at the end of the interval: inhibitions and the
+# rate factors that enter eq. 8, then the six ion fractions
+F_ALG_END = 220
+# bytes per particle and interval: state in and out, T, D, feed index, the
+# particle's feed row (26 entries), S_H+ in and out, status, Newton tally
+BYTES_FIXED = 35 * 8 * 2 + 8 + 8 + 4 + 26 * 8 + 16 + 1 + 4
+
+
+def fixed_flops(method: str, substeps: int, newton: int, particles: int) -> float:
+    """Algorithmic flops of `particles` particle-intervals of the fixed-step
+    scheme (`substeps` explicit steps each) that took `newton` algebraic
+    iterations in all."""
+    if method == "euler":
+        per = F_RHS_BASE + F_EULER_VECTOR
+    else:
+        per = 4 * F_RHS_BASE + F_RK4_VECTOR
+    return float(particles) * (F_TCONST + F_ALG_END + substeps * per) + float(newton) * F_NEWTON
