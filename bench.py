@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector, FLOP/s
 PEAK_HBM = 8.0e12    # bytes/s
+# the paper's thread-scaling run (sec. 4.3): CSTR particles of the fixed path
+FIXED_PARTICLES = 110_929
 
 # Sources of the step kernel: HBM traffic measured with hardware counters is
 # reported only while they are unchanged since the measurement.
@@ -155,7 +157,7 @@ def cpu_baseline(w, rtol, n_sample, steps):
 def main():
     args = parse()
     if args.n is None:
-        args.n = {"surrogate": 1 << 24, "fixed": 110_929}.get(args.path, 1 << 20)
+        args.n = {"surrogate": 1 << 24, "fixed": FIXED_PARTICLES}.get(args.path, 1 << 20)
     if args.steps is None:
         args.steps = {"surrogate": 96, "fixed": 100}.get(args.path, 10)
     if args.gpus != 1:
