@@ -193,6 +193,44 @@ int adm1_step_fixed(adm1_ctx *ctx, double *state, int64_t ld, const double *temp
                     const adm1_feed *feed, double dt_days, int32_t substeps, int32_t method,
                     int64_t n, double *H, uint8_t *status, int32_t *newton, void *stream);
 
+/* Diffusion between particles (the paper names it as the missing transport
+ * term besides advection, sec. 2.3, and as its next step).  Operator (the
+ * paper fixes none): the SPH diffusion form on equal particle volumes V_p,
+ * dC_i/dt = 2 D V_p sum_{j != i, r_ij < 2h} (C_i - C_j) W'(r_ij)/r_ij with
+ * the 3-D Wendland C2 kernel of support 2h, on the 13 soluble differential
+ * entries (S_su..S_ac, S_ch4, S_IC, S_IN, S_I, S_cat, S_an); explicit Euler
+ * substeps.  The algebraic entries are refreshed by the next reaction step.
+ * Neighbours are found on a uniform grid of cells of edge 2h over the box
+ * [lo, hi] (particles outside it are clamped into the edge cells, which
+ * stays exact, only slower).  Explicit Euler is stable for roughly
+ * dt/substeps < 0.1 spacing^2 / D; the caller chooses substeps. */
+typedef struct adm1_diffusion {
+    double h;     /* smoothing length (m) */
+    double D;     /* diffusivity of the soluble entries (m2/d) */
+    double V_p;   /* liquid volume of every particle (m3) */
+    double lo[3]; /* box of the neighbour grid (m) */
+    double hi[3];
+} adm1_diffusion;
+
+typedef struct adm1_grid adm1_grid;
+
+/* Allocate a neighbour grid for up to n_max particles (cell arrays, the
+ * particle order and copies in cell order: about 130 B per particle and 8 B
+ * per cell).  ADM1_E_OPTS if a parameter is not positive and finite or the
+ * grid would exceed 2^26 cells; ADM1_E_SIZE for n_max outside 1..2^31-1. */
+int adm1_grid_create(const adm1_diffusion *d, int64_t n_max, adm1_grid **out);
+void adm1_grid_destroy(adm1_grid *g);
+
+/* Diffuse the soluble entries of particles 0..n-1 over dt_days in
+ * `substeps` explicit steps, IN PLACE.  state: [35][ld] float64; pos:
+ * float32 [3][ld] positions (m, the layout of adm1_advect); neighbours
+ * (nullable, [n] int32): number of particles within 2h of each.  Sums run in
+ * a fixed order (cells, then ascending particle index), so results repeat
+ * bit for bit.  Asynchronous on `stream`, no allocation; calls that share a
+ * grid must not overlap. */
+int adm1_diffuse(adm1_grid *g, double *state, int64_t ld, const float *pos, int64_t n,
+                 double dt_days, int32_t substeps, int32_t *neighbours, void *stream);
+
 /* Headspace gas flows (sec. 1: release of gaseous components) of particles
  * 0..n-1: q_gas = V_liq k_p max(0, P_gas - P_atm) P_gas / P_atm and
  * q_ch4 = q_gas p_ch4 / P_gas (m3/d), with P_gas the sum of the partial

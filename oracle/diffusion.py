@@ -76,6 +76,26 @@ def diffusion_rate(pos, C, h, V_p, D, chunk=256):
     return rate, absum
 
 
+def diffusion_rate_at(pos, C, idx, h, V_p, D):
+    """dC/dt of the particles idx only, each against all particles (for
+    sampled checks of large populations).  Returns (rate [k][len(idx)],
+    neighbour counts [len(idx)])."""
+    pos = np.asarray(pos, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    out = np.zeros((C.shape[0], len(idx)))
+    cnt = np.zeros(len(idx), dtype=np.int64)
+    for m, i in enumerate(idx):
+        d = pos - pos[:, i:i + 1]
+        r = np.sqrt((d * d).sum(axis=0))
+        mask = r < 2.0 * h
+        mask[i] = False
+        j = np.nonzero(mask)[0]
+        F = kernel_f(r[j], h)
+        out[:, m] = 2.0 * D * V_p * ((C[:, i:i + 1] - C[:, j]) * F[None]).sum(axis=1)
+        cnt[m] = len(j)
+    return out, cnt
+
+
 def neighbour_counts(pos, h, chunk=256):
     """Number of particles j != i within r < 2h of each particle i."""
     pos = np.asarray(pos, dtype=np.float64)

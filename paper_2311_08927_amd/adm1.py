@@ -90,6 +90,11 @@ def lib():
         L.adm1_advect.argtypes = [vp, i64, i64, vp, dbl, i32, vp]
         L.adm1_feed_mask.restype = ctypes.c_int
         L.adm1_feed_mask.argtypes = [vp, i64, i64, dbl, dbl, dbl, i32, i32, vp, vp, vp, vp]
+        L.adm1_grid_create.restype = ctypes.c_int
+        L.adm1_grid_create.argtypes = [vp, i64, ctypes.POINTER(vp)]
+        L.adm1_grid_destroy.argtypes = [vp]
+        L.adm1_diffuse.restype = ctypes.c_int
+        L.adm1_diffuse.argtypes = [vp, vp, i64, vp, i64, dbl, i32, vp, vp]
         _lib = L
     return _lib
 
@@ -234,6 +239,59 @@ def make_flow(d: dict) -> adm1_flow:
     return adm1_flow(d["omega"], d["R"], d["H"],
                      (ctypes.c_double * FLOW_MODES)(*(a + [0.0] * (FLOW_MODES - len(a)))),
                      len(a))
+
+
+class adm1_diffusion(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("D", ctypes.c_double), ("V_p", ctypes.c_double),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+def make_diffusion(h, D, V_p, lo, hi) -> adm1_diffusion:
+    return adm1_diffusion(float(h), float(D), float(V_p), (ctypes.c_double * 3)(*lo),
+                          (ctypes.c_double * 3)(*hi))
+
+
+def adm1_grid_create(d: adm1_diffusion, n_max: int, check=True):
+    out = ctypes.c_void_p()
+    rc = lib().adm1_grid_create(ctypes.byref(d), int(n_max), ctypes.byref(out))
+    if check:
+        _check(rc, "adm1_grid_create")
+    return out.value if rc == 0 else rc
+
+
+def adm1_grid_destroy(g):
+    lib().adm1_grid_destroy(g)
+
+
+def adm1_diffuse(g, state, ld, pos, n, dt_days, substeps, neighbours=None, stream=None,
+                 check=True) -> int:
+    rc = lib().adm1_diffuse(g, _ptr(state), int(ld), _ptr(pos), int(n), float(dt_days),
+                            int(substeps), _ptr(neighbours), _stream(stream))
+    if check:
+        _check(rc, "adm1_diffuse")
+    return rc
+
+
+class Grid:
+    """Owner of an adm1_grid (the neighbour grid of adm1_diffuse)."""
+
+    def __init__(self, d: adm1_diffusion, n_max: int):
+        self.handle = adm1_grid_create(d, n_max)
+
+    def diffuse(self, state, pos, n, dt_days, substeps=1, neighbours=None, stream=None):
+        adm1_diffuse(self.handle, state, state.shape[1], pos, n, dt_days, substeps, neighbours,
+                     stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            adm1_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def adm1_advect(pos, ld, n, flow: adm1_flow, dt_seconds, substeps, stream=None):
