@@ -324,9 +324,11 @@ typedef struct adm1_flow {
     int32_t nmodes;
 } adm1_flow;
 
-/* Move particles 0..n-1 for dt_seconds with `substeps` classical RK4
- * substeps in the field; positions stay inside the tank (radial and axial
- * clamp).  pos: float32 [3][ld] device array (x, y, z in m), in place. */
+/* Move particles 0..n-1 for dt_seconds in `substeps` equal substeps: a
+ * classical RK4 step of the meridional (axisymmetric) modes, then the exact
+ * turn by omega h (the two commute); positions stay inside the tank (radial
+ * and axial clamp).  pos: float32 [3][ld] device array (x, y, z in m), in
+ * place. */
 int adm1_advect(float *pos, int64_t ld, int64_t n, const adm1_flow *flow, double dt_seconds,
                 int32_t substeps, void *stream);
 
