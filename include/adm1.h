@@ -200,7 +200,7 @@ int adm1_step_fixed(adm1_ctx *ctx, double *state, int64_t ld, const double *temp
  * the 3-D Wendland C2 kernel of support 2h, on the 13 soluble differential
  * entries (S_su..S_ac, S_ch4, S_IC, S_IN, S_I, S_cat, S_an); explicit Euler
  * substeps.  The algebraic entries are refreshed by the next reaction step.
- * Neighbours are found on a uniform grid of cells of edge 2h over the box
+ * Neighbours are found on a uniform grid of cells of edge h over the box
  * [lo, hi] (particles outside it are clamped into the edge cells, which
  * stays exact, only slower).  Explicit Euler is stable for roughly
  * dt/substeps < 0.1 spacing^2 / D; the caller chooses substeps. */
@@ -215,9 +215,10 @@ typedef struct adm1_diffusion {
 typedef struct adm1_grid adm1_grid;
 
 /* Allocate a neighbour grid for up to n_max particles (cell arrays, the
- * particle order and copies in cell order: about 130 B per particle and 8 B
+ * particle order and copies in cell order: about 150 B per particle and 8 B
  * per cell).  ADM1_E_OPTS if a parameter is not positive and finite or the
- * grid would exceed 2^26 cells; ADM1_E_SIZE for n_max outside 1..2^31-1. */
+ * grid (cells of edge h over the box) would exceed 2^26 cells; ADM1_E_SIZE
+ * for n_max outside 1..2^31-1. */
 int adm1_grid_create(const adm1_diffusion *d, int64_t n_max, adm1_grid **out);
 void adm1_grid_destroy(adm1_grid *g);
 

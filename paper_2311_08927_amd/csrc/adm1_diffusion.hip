@@ -9,19 +9,25 @@
 // a = 21 / (16 pi h^3), on the 13 soluble differential entries, advanced by
 // explicit Euler substeps.
 //
-// Neighbour search: cells of edge 2h (the kernel support) over a fixed box,
-// so every neighbour of a particle lies in the 27 cells around its own.  Per
+// Neighbour search: cells of edge h (half the kernel support) over a fixed
+// box, so every neighbour of a particle lies in the 5 x 5 x 5 cells around
+// its own (a search volume of 125 h^3 against 216 h^3 with cells of edge
+// 2h).  Per
 // call (positions are fixed over the interval):
 //   k_grid_count   -- cell of every particle (clamped into the box), counts;
 //   k_scan_*       -- exclusive prefix sums of the counts (cell starts);
 //   k_grid_place   -- scatter of the particle indices into cell order;
 //   k_grid_sort    -- one thread per cell sorts its indices ascending, so the
 //                     order, and with it every sum, is the same run to run;
-//   k_gather_pos   -- positions in cell order;
-// then per substep k_gather_c copies the soluble entries into cell order and
-// k_diffuse, one thread per particle in cell order (neighbouring threads
-// read the same cells), sums over the 27 cells and adds the Euler update to
-// the state.  Every launch is bounded by n or by the cell count; indices
+//   k_gather_pos   -- positions in cell order, one float4 per particle;
+// then per substep k_gather_c copies the soluble entries into cell order
+// (one 128-byte row of kCRow doubles per particle) and k_diffuse, one thread
+// per particle in cell order (neighbouring threads read the same cells),
+// sums over those cells (25 index ranges: the five cells of a row along x
+// are consecutive) and adds the Euler update to the state.  A
+// candidate is first tested in FP32 against a slightly enlarged radius; the
+// FP64 test then decides, so the neighbour sets are those of an FP64
+// distance test.  Every launch is bounded by n or by the cell count; indices
 // read back from the grid are < n by construction.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -35,6 +41,9 @@ namespace adm1 {
 namespace {
 
 constexpr int kDiffRows = 13;
+// cells of edge 2h / kSub: the support 2h spans kSub cells each way
+constexpr int kSub = 2;
+constexpr int kCRow = 16;  // doubles per particle row of the cell-ordered copy
 constexpr int kScanThreads = 256;
 constexpr int kScanPer = 8;
 constexpr int kScanChunk = kScanThreads * kScanPer;
@@ -194,38 +203,36 @@ __global__ void __launch_bounds__(256) k_grid_sort(const int32_t* __restrict__ s
 
 __global__ void __launch_bounds__(256) k_gather_pos(const int32_t* __restrict__ sorted,
                                                     const float* __restrict__ pos, int64_t ld,
-                                                    int64_t n, float* __restrict__ spos,
-                                                    int64_t lds)
+                                                    int64_t n, float4* __restrict__ spos)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = sorted[s];
-    spos[s] = pos[i];
-    spos[lds + s] = pos[ld + i];
-    spos[2 * lds + s] = pos[2 * ld + i];
+    spos[s] = float4{pos[i], pos[ld + i], pos[2 * ld + i], 0.0f};
 }
 
 __global__ void __launch_bounds__(256) k_gather_c(const int32_t* __restrict__ sorted,
                                                   const double* __restrict__ state, int64_t ld,
-                                                  int64_t n, double* __restrict__ sc,
-                                                  int64_t lds)
+                                                  int64_t n, double* __restrict__ sc)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = sorted[s];
+    double* row = sc + s * kCRow;
 #pragma unroll
-    for (int k = 0; k < kDiffRows; ++k) sc[k * lds + s] = state[diff_row(k) * ld + i];
+    for (int k = 0; k < kDiffRows; ++k) row[k] = state[diff_row(k) * ld + i];
 }
 
 struct DiffArgs {
     GridGeom g;
     const int32_t* start;
     const int32_t* sorted;
-    const float* spos;
-    const double* sc;
-    int64_t lds, n;
+    const float4* spos;
+    const double* sc;  // [n_max][kCRow]
+    int64_t n;
     double* state;
     int64_t ld;
+    float h2x4_pre;  // (2h)^2 (1 + 1e-4): FP32 prefilter, never below the FP64 test
     double h2x4;     // (2h)^2
     double inv_h;
     double fcoef;    // -5 a / h^2
@@ -237,47 +244,52 @@ __global__ void __launch_bounds__(256) k_diffuse(DiffArgs a)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.n) return;
-    const float xs = a.spos[s], ys = a.spos[a.lds + s], zs = a.spos[2 * a.lds + s];
+    const float4 ps = a.spos[s];
+    const float xs = ps.x, ys = ps.y, zs = ps.z;
     double cs[kDiffRows], acc[kDiffRows];
 #pragma unroll
     for (int k = 0; k < kDiffRows; ++k) {
-        cs[k] = a.sc[k * a.lds + s];
+        cs[k] = a.sc[s * kCRow + k];
         acc[k] = 0.0;
     }
     int cx, cy, cz;
     cell_coords(a.g, xs, ys, zs, cx, cy, cz);
     int cnt = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
+    for (int dz = -kSub; dz <= kSub; ++dz) {
         const int z = cz + dz;
         if (z < 0 || z >= a.g.nc[2]) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
+        for (int dy = -kSub; dy <= kSub; ++dy) {
             const int y = cy + dy;
             if (y < 0 || y >= a.g.nc[1]) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int x = cx + dx;
-                if (x < 0 || x >= a.g.nc[0]) continue;
-                const int c = (z * a.g.nc[1] + y) * a.g.nc[0] + x;
-                const int32_t e = a.start[c + 1];
-                for (int32_t j = a.start[c]; j < e; ++j) {
-                    if (j == s) continue;
-                    const double ddx = (double)xs - (double)a.spos[j];
-                    const double ddy = (double)ys - (double)a.spos[a.lds + j];
-                    const double ddz = (double)zs - (double)a.spos[2 * a.lds + j];
-                    const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                    if (!(r2 < a.h2x4)) continue;
-                    const double t = 1.0 - 0.5 * sqrt(r2) * a.inv_h;
-                    const double F = a.fcoef * t * t * t;
-                    ++cnt;
+            // the cells x-kSub..x+kSub of a row are consecutive in cell
+            // order, and so are their particles: one index range per row
+            const int x0 = cx > kSub ? cx - kSub : 0;
+            const int x1 = cx + kSub < a.g.nc[0] ? cx + kSub : a.g.nc[0] - 1;
+            const int c0 = (z * a.g.nc[1] + y) * a.g.nc[0] + x0;
+            const int32_t e = a.start[c0 + (x1 - x0) + 1];
+            for (int32_t j = a.start[c0]; j < e; ++j) {
+                if (j == s) continue;
+                const float4 pj = a.spos[j];
+                const float fx = xs - pj.x, fy = ys - pj.y, fz = zs - pj.z;
+                if (!(fx * fx + fy * fy + fz * fz < a.h2x4_pre)) continue;
+                const double ddx = (double)xs - (double)pj.x;
+                const double ddy = (double)ys - (double)pj.y;
+                const double ddz = (double)zs - (double)pj.z;
+                const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                if (!(r2 < a.h2x4)) continue;
+                const double t = 1.0 - 0.5 * sqrt(r2) * a.inv_h;
+                const double F = a.fcoef * t * t * t;
+                ++cnt;
+                const double* cj = a.sc + (int64_t)j * kCRow;
 #pragma unroll
-                    for (int k = 0; k < kDiffRows; ++k)
-                        acc[k] = fma(cs[k] - a.sc[k * a.lds + j], F, acc[k]);
-                }
+                for (int k = 0; k < kDiffRows; ++k) acc[k] = fma(cs[k] - cj[k], F, acc[k]);
             }
         }
     }
     const int64_t id = a.sorted[s];
 #pragma unroll
-    for (int k = 0; k < kDiffRows; ++k) a.state[diff_row(k) * a.ld + id] = fma(a.scale, acc[k], cs[k]);
+    for (int k = 0; k < kDiffRows; ++k)
+        a.state[diff_row(k) * a.ld + id] = fma(a.scale, acc[k], cs[k]);
     if (a.neighbours) a.neighbours[id] = cnt;
 }
 
@@ -303,7 +315,7 @@ struct adm1_grid {
     adm1::GridGeom g;
     int64_t n_max, ncell, nblk;
     int32_t *cell, *count, *start, *sorted, *bsum;
-    float* spos;
+    float4* spos;
     double* sc;
 };
 
@@ -322,11 +334,12 @@ int adm1_grid_create(const adm1_diffusion* d, int64_t n_max, adm1_grid** out)
     for (int k = 0; k < 3; ++k) {
         const double ext = d->hi[k] - d->lo[k];
         if (!(ext > 0.0) || !std::isfinite(ext) || !std::isfinite(d->lo[k])) return ADM1_E_OPTS;
-        const double nc = std::ceil(ext / (2.0 * d->h));
+        const double cs = 2.0 * d->h / adm1::kSub;
+        const double nc = std::ceil(ext / cs);
         if (nc > (double)(1 << 20)) return ADM1_E_OPTS;
         g.nc[k] = nc < 1.0 ? 1 : (int)nc;
         g.lo[k] = d->lo[k];
-        g.inv_cs[k] = 1.0 / (2.0 * d->h);
+        g.inv_cs[k] = 1.0 / cs;
         cells *= g.nc[k];
     }
     if (cells > (double)(1 << 26)) return ADM1_E_OPTS;
@@ -345,8 +358,8 @@ int adm1_grid_create(const adm1_diffusion* d, int64_t n_max, adm1_grid** out)
               hipMalloc((void**)&p->count, p->ncell * sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void**)&p->start, (p->ncell + 1) * sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void**)&p->bsum, p->nblk * sizeof(int32_t)) == hipSuccess &&
-              hipMalloc((void**)&p->spos, 3 * n_max * sizeof(float)) == hipSuccess &&
-              hipMalloc((void**)&p->sc, adm1::kDiffRows * n_max * sizeof(double)) == hipSuccess;
+              hipMalloc((void**)&p->spos, n_max * sizeof(float4)) == hipSuccess &&
+              hipMalloc((void**)&p->sc, adm1::kCRow * n_max * sizeof(double)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         adm1_grid_destroy(p);
@@ -394,9 +407,8 @@ int adm1_diffuse(adm1_grid* g, double* state, int64_t ld, const float* pos, int6
                        g->start, g->count, g->sorted);
     hipLaunchKernelGGL(k_grid_sort, dim3(blocks(m, 256)), dim3(256), 0, s, g->start, m,
                        g->sorted);
-    const int64_t lds = g->n_max;
     hipLaunchKernelGGL(k_gather_pos, dim3(blocks(n, 256)), dim3(256), 0, s, g->sorted, pos, ld,
-                       n, g->spos, lds);
+                       n, g->spos);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
     const double h = g->d.h;
@@ -406,18 +418,18 @@ int adm1_diffuse(adm1_grid* g, double* state, int64_t ld, const float* pos, int6
     a.sorted = g->sorted;
     a.spos = g->spos;
     a.sc = g->sc;
-    a.lds = lds;
     a.n = n;
     a.state = state;
     a.ld = ld;
     a.h2x4 = 4.0 * h * h;
+    a.h2x4_pre = (float)(a.h2x4 * (1.0 + 1e-4));
     a.inv_h = 1.0 / h;
     a.fcoef = -5.0 * (21.0 / (16.0 * M_PI * h * h * h)) / (h * h);
     a.scale = dt_days / substeps * 2.0 * g->d.D * g->d.V_p;
     for (int k = 0; k < substeps; ++k) {
         a.neighbours = k == 0 ? neighbours : nullptr;
         hipLaunchKernelGGL(k_gather_c, dim3(blocks(n, 256)), dim3(256), 0, s, g->sorted, state,
-                           ld, n, g->sc, lds);
+                           ld, n, g->sc);
         hipLaunchKernelGGL(k_diffuse, dim3(blocks(n, 256)), dim3(256), 0, s, a);
     }
     e = hipGetLastError();
