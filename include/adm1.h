@@ -55,7 +55,8 @@ enum {
     ADM1_E_FEED = -6,        /* feed table invalid (n_feed < 1) */
     ADM1_E_NOMEM = -7,       /* context scratch allocation failed (adm1_init) */
     ADM1_E_VARIANT = -8,     /* unknown kernel variant */
-    ADM1_E_DT = -9           /* dt not positive and finite */
+    ADM1_E_DT = -9,          /* dt not positive and finite */
+    ADM1_E_IO = -10          /* snapshot file missing, unreadable, unwritable or malformed */
 };
 
 /* Status codes written per particle. */
@@ -231,6 +232,36 @@ void adm1_grid_destroy(adm1_grid *g);
  * grid must not overlap. */
 int adm1_diffuse(adm1_grid *g, double *state, int64_t ld, const float *pos, int64_t n,
                  double dt_days, int32_t substeps, int32_t *neighbours, void *stream);
+
+/* Binary particle snapshots: the particle data exchanged with the flow
+ * solver every coupling step (sec. 2.3), which the paper moves as ASCII and
+ * names a main bottleneck (sec. 4.3).  File layout (little endian): a 64-byte
+ * header ("ADM1SNAP", uint32 version 1, uint32 field mask, uint64 n, float64
+ * time in s, 32 zero bytes), then the rows of each present field in mask-bit
+ * order: positions float32 [3][n] (m), velocities float32 [3][n] (m/s),
+ * densities float32 [n] (kg/m3), states float64 [35][n].  All buffers are
+ * HOST memory (pinned memory makes the following device copy fastest), laid
+ * out like the device arrays: row r of a field starts at r * ld elements.
+ * Rows move with positional reads / writes of 8 MB chunks on up to 8
+ * threads.  Synchronous. */
+enum { ADM1_SNAP_POS = 1, ADM1_SNAP_VEL = 2, ADM1_SNAP_RHO = 4, ADM1_SNAP_STATE = 8 };
+
+/* Write particles 0..n-1 of the non-NULL fields to `path` (replaced).
+ * ADM1_E_SIZE unless 0 <= n <= ld, ld >= 1; ADM1_E_IO on a failed open or
+ * write. */
+int adm1_snapshot_write(const char *path, int64_t n, int64_t ld, double time_s, const float *pos,
+                        const float *vel, const float *rho, const double *state);
+
+/* Particle count, field mask and time of a snapshot (each output nullable).
+ * ADM1_E_IO if the file is missing or not a snapshot. */
+int adm1_snapshot_info(const char *path, int64_t *n, uint32_t *fields, double *time_s);
+
+/* Read the fields whose destinations are non-NULL; *n_out (nullable) gets
+ * the particle count.  ADM1_E_IO if the file is missing, malformed, shorter
+ * or longer than its header says, or lacks a requested field; ADM1_E_SIZE if
+ * ld < n.  Nothing is guaranteed about the destinations after an error. */
+int adm1_snapshot_read(const char *path, int64_t ld, float *pos, float *vel, float *rho,
+                       double *state, int64_t *n_out);
 
 /* Headspace gas flows (sec. 1: release of gaseous components) of particles
  * 0..n-1: q_gas = V_liq k_p max(0, P_gas - P_atm) P_gas / P_atm and

@@ -20,7 +20,8 @@ NX, ND, NLIQ = 35, 28, 26
 
 VARIANT_DENSE1, VARIANT_SPARSE1, VARIANT_SPARSE2 = 0, 1, 2
 ERRORS = {0: "ok", -1: "E_NULL", -2: "E_SIZE", -3: "E_NOT_DEVICE", -4: "E_PARAMS",
-          -5: "E_OPTS", -6: "E_FEED", -7: "E_NOMEM", -8: "E_VARIANT", -9: "E_DT"}
+          -5: "E_OPTS", -6: "E_FEED", -7: "E_NOMEM", -8: "E_VARIANT", -9: "E_DT",
+          -10: "E_IO"}
 
 _lib = None
 

@@ -16,7 +16,7 @@ LIB = os.path.join(PKG, "libadm1.so")
 ARCH = os.environ.get("ADM1_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["adm1_abi.hip", "adm1_kernels.hip", "adm1_step_sparse2.hip", "adm1_order.hip",
            "adm1_transport.hip", "adm1_mlp.hip", "adm1_surrogate.hip",
-           "adm1_diffusion.hip"]
+           "adm1_diffusion.hip", "adm1_snapshot.cpp"]
 
 
 def hipcc() -> str:

@@ -268,6 +268,7 @@ const char* adm1_strerror(int code)
     case ADM1_E_NOMEM: return "context scratch allocation failed";
     case ADM1_E_VARIANT: return "unknown step-kernel variant";
     case ADM1_E_DT: return "dt must be positive and finite";
+    case ADM1_E_IO: return "snapshot file missing, unreadable, unwritable or malformed";
     default: break;
     }
     if (code > 0) return hipGetErrorString((hipError_t)code);
