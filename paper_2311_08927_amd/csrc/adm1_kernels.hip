@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(64, 1) k_step1(StepArgs a)
 // non-finite state, 4 non-finite or invalid input; bit 0x80 flags a negative
 // differential entry.  A failed particle keeps its input.
 template <typename R, int M>
-__global__ void __launch_bounds__(64) k_fixed(FixedArgs a)
+__device__ __forceinline__ void fixed_body(const FixedArgs& a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
@@ -327,12 +327,20 @@ __global__ void __launch_bounds__(64) k_fixed(FixedArgs a)
         const double h = a.dt / a.substeps;
         double f[NY];
         for (int s = 0; s < a.substeps && st == 0; ++s) {
+            // Euler re-reads the feed row every substep (an empty asm hides
+            // the pointer) instead of holding 26 inflows in registers
+            // throughout; RK4, at one wave per SIMD anyway, keeps them
+            const double* sinv = sin;
+            if (M == 0) asm volatile("" : "+v"(sinv));
             if (M == 0) {
-                if (rhs<R>(p, c, y, D, sin, H, Sh2, f, it)) {
+                // Euler update written in place: rhs_in reads every entry for
+                // the last time in the expression of its own derivative, so
+                // y[k] may take its new value as soon as f_k is formed
+                if (rhs_in<R>(p, c, y, D, FeedInflow{D, sinv}, H, Sh2,
+                              [&y, h](int k, double v) { y[k] = fma(h, v, y[k]); }, it)) {
                     st = 1;
                     break;
                 }
-                for (int k = 0; k < NY; ++k) y[k] = fma(h, f[k], y[k]);
             } else {
                 double y0[NY], acc[NY];
                 for (int k = 0; k < NY; ++k) y0[k] = y[k];
@@ -340,7 +348,7 @@ __global__ void __launch_bounds__(64) k_fixed(FixedArgs a)
                 const double wt[3] = {1.0, 2.0, 2.0};
                 const double ah[3] = {0.5 * h, 0.5 * h, h};
                 for (int q = 0; q < 3 && st == 0; ++q) {
-                    if (rhs<R>(p, c, y, D, sin, H, Sh2, f, it)) {
+                    if (rhs<R>(p, c, y, D, sinv, H, Sh2, f, it)) {
                         st = 1;
                         break;
                     }
@@ -350,7 +358,7 @@ __global__ void __launch_bounds__(64) k_fixed(FixedArgs a)
                     }
                 }
                 if (st) break;
-                if (rhs<R>(p, c, y, D, sin, H, Sh2, f, it)) {
+                if (rhs<R>(p, c, y, D, sinv, H, Sh2, f, it)) {
                     st = 1;
                     break;
                 }
@@ -371,6 +379,20 @@ __global__ void __launch_bounds__(64) k_fixed(FixedArgs a)
     }
     a.status[i] = (uint8_t)st;
     if (a.newton) a.newton[i] = it;
+}
+
+// Euler fits two waves per SIMD (its state is updated in place); RK4 keeps
+// four stage vectors and runs at one wave per SIMD without spills.
+template <typename R>
+__global__ void __launch_bounds__(64, 2) k_fixed_euler(FixedArgs a)
+{
+    fixed_body<R, 0>(a);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(64) k_fixed_rk4(FixedArgs a)
+{
+    fixed_body<R, 1>(a);
 }
 
 template <typename R>
@@ -521,14 +543,14 @@ hipError_t launch_fixed(const FixedArgs& a, int rate_precision, hipStream_t s)
     if (grid == 0) return hipSuccess;
     if (a.method == 0) {
         if (rate_precision)
-            hipLaunchKernelGGL((k_fixed<float, 0>), dim3(grid), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(k_fixed_euler<float>, dim3(grid), dim3(64), 0, s, a);
         else
-            hipLaunchKernelGGL((k_fixed<double, 0>), dim3(grid), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(k_fixed_euler<double>, dim3(grid), dim3(64), 0, s, a);
     } else {
         if (rate_precision)
-            hipLaunchKernelGGL((k_fixed<float, 1>), dim3(grid), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(k_fixed_rk4<float>, dim3(grid), dim3(64), 0, s, a);
         else
-            hipLaunchKernelGGL((k_fixed<double, 1>), dim3(grid), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(k_fixed_rk4<double>, dim3(grid), dim3(64), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -125,7 +125,6 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
 constexpr int TM = 64;       // rows per block
 constexpr int RT = TM / 16;  // row tiles
 constexpr int LDH = 264;     // LDS row stride (BF16 elements): 528 B, 16-byte aligned
-constexpr int kThreads = 256;    // generic GEMM
 constexpr int kFwdWaves = 8;     // forward: waves per block
 constexpr int kFwdThreads = 64 * kFwdWaves;
 
