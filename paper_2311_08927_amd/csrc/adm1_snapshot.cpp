@@ -61,8 +61,10 @@ constexpr Field kFields[4] = {{ADM1_SNAP_POS, 3, 4}, {ADM1_SNAP_VEL, 3, 4},
                               {ADM1_SNAP_RHO, 1, 4}, {ADM1_SNAP_STATE, 35, 8}};
 
 // Move every piece with pread/pwrite in chunks, on up to kThreads threads.
-bool transfer(int fd, const std::vector<Piece>& pieces, bool write)
-{
+// False on an I/O error; thread or memory exhaustion also ends in false
+// (nothing is thrown across the C interface).
+bool transfer(int fd, const std::vector<Piece>& pieces, bool write) noexcept
+try {
     std::vector<Piece> chunks;
     for (const Piece& p : pieces)
         for (int64_t o = 0; o < p.bytes; o += kChunk)
@@ -87,10 +89,18 @@ bool transfer(int fd, const std::vector<Piece>& pieces, bool write)
     };
     const int nt = (int)std::min<size_t>(kThreads, std::max<size_t>(1, chunks.size()));
     std::vector<std::thread> pool;
-    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    pool.reserve(nt);
+    try {
+        for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    } catch (...) {
+        // fewer helper threads than asked for: the ones started and this
+        // thread still finish every chunk
+    }
     work();
     for (auto& t : pool) t.join();
     return ok;
+} catch (...) {
+    return false;
 }
 
 int read_header(int fd, Header& h)
@@ -102,13 +112,40 @@ int read_header(int fd, Header& h)
     return ADM1_OK;
 }
 
+// The fields of a checked header whose destinations are non-NULL.
+int read_fields(int fd, const Header& h, int64_t ld, void* const dst[4]) noexcept
+try {
+    const int64_t n = (int64_t)h.n;
+    std::vector<Piece> pieces;
+    int64_t off = kHeader;
+    int rc = ADM1_OK;
+    for (int f = 0; f < 4; ++f) {
+        const bool present = (h.fields & kFields[f].bit) != 0;
+        if (dst[f] && !present) rc = ADM1_E_IO;
+        if (!present) continue;
+        for (int r = 0; r < kFields[f].rows; ++r) {
+            if (dst[f])
+                pieces.push_back({off, (char*)dst[f] + (int64_t)r * ld * kFields[f].elem,
+                                  n * kFields[f].elem});
+            off += n * kFields[f].elem;
+        }
+    }
+    struct stat st;
+    if (!rc && ld < n) rc = ADM1_E_SIZE;
+    if (!rc && (fstat(fd, &st) != 0 || st.st_size != off)) rc = ADM1_E_IO;
+    if (!rc && !transfer(fd, pieces, false)) rc = ADM1_E_IO;
+    return rc;
+} catch (...) {
+    return ADM1_E_IO;
+}
+
 }  // namespace
 
 extern "C" {
 
 int adm1_snapshot_write(const char* path, int64_t n, int64_t ld, double time_s, const float* pos,
                         const float* vel, const float* rho, const double* state)
-{
+try {
     if (!path) return ADM1_E_NULL;
     if (n < 0 || ld < n || ld < 1) return ADM1_E_SIZE;
     Header h;
@@ -135,6 +172,8 @@ int adm1_snapshot_write(const char* path, int64_t n, int64_t ld, double time_s, 
               transfer(fd, pieces, true);
     ok = (close(fd) == 0) && ok;
     return ok ? ADM1_OK : ADM1_E_IO;
+} catch (...) {
+    return ADM1_E_IO;
 }
 
 int adm1_snapshot_info(const char* path, int64_t* n, uint32_t* fields, double* time_s)
@@ -160,31 +199,12 @@ int adm1_snapshot_read(const char* path, int64_t ld, float* pos, float* vel, flo
     if (fd < 0) return ADM1_E_IO;
     Header h;
     int rc = read_header(fd, h);
-    if (rc) {
-        close(fd);
-        return rc;
+    if (!rc) {
+        void* const dst[4] = {pos, vel, rho, state};
+        rc = read_fields(fd, h, ld, dst);
     }
-    const int64_t n = (int64_t)h.n;
-    struct stat st;
-    void* dst[4] = {pos, vel, rho, state};
-    std::vector<Piece> pieces;
-    int64_t off = kHeader;
-    for (int f = 0; f < 4; ++f) {
-        const bool present = (h.fields & kFields[f].bit) != 0;
-        if (dst[f] && !present) rc = ADM1_E_IO;
-        if (!present) continue;
-        for (int r = 0; r < kFields[f].rows; ++r) {
-            if (dst[f])
-                pieces.push_back({off, (char*)dst[f] + (int64_t)r * ld * kFields[f].elem,
-                                  n * kFields[f].elem});
-            off += n * kFields[f].elem;
-        }
-    }
-    if (!rc && ld < n) rc = ADM1_E_SIZE;
-    if (!rc && (fstat(fd, &st) != 0 || st.st_size != off)) rc = ADM1_E_IO;
-    if (!rc && !transfer(fd, pieces, false)) rc = ADM1_E_IO;
     close(fd);
-    if (!rc && n_out) *n_out = n;
+    if (!rc && n_out) *n_out = (int64_t)h.n;
     return rc;
 }
 
