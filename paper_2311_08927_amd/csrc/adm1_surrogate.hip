@@ -270,7 +270,13 @@ bool dalloc(adm1_surrogate* s, T*& p, int64_t count)
         p = nullptr;
         return false;
     }
-    s->allocs.push_back((void*)p);
+    try {
+        s->allocs.push_back((void*)p);
+    } catch (...) {
+        (void)hipFree(p);
+        p = nullptr;
+        return false;
+    }
     return true;
 }
 
@@ -370,7 +376,7 @@ int adm1_surrogate_create(adm1_ctx* ctx, int64_t n_max, int64_t batch_max, adm1_
          dalloc(s, s->dZ, B * kMlpHidden) && dalloc(s, s->dZb, B * kMlpHidden) &&
          dalloc(s, s->dZT, ldt * kMlpHidden) && dalloc(s, s->split, split) &&
          dalloc(s, s->lossp, (B * kMlpOutPad + 255) / 256 + 1);
-    if (ok) {
+    if (ok) try {
         // zero parameters and moments; mask of the real entries
         std::vector<uint8_t> mask((size_t)np, 0);
         for (int l = 0; l < kMlpLayers; ++l) {
@@ -388,6 +394,8 @@ int adm1_surrogate_create(adm1_ctx* ctx, int64_t n_max, int64_t batch_max, adm1_
              hipMemset(s->norm, 0, kMlpNorm * sizeof(float)) == hipSuccess &&
              hipMemset(s->floor_, 0, NX * sizeof(double)) == hipSuccess &&
              hipMemcpy(s->mask, mask.data(), (size_t)np, hipMemcpyHostToDevice) == hipSuccess;
+    } catch (...) {
+        ok = false;
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -407,7 +415,7 @@ void adm1_surrogate_destroy(adm1_surrogate* s)
 }
 
 int adm1_surrogate_set_weights(adm1_surrogate* s, const float* params, const adm1_mlp_norm* norm)
-{
+try {
     int rc = check_surrogate(s);
     if (rc) return rc;
     if (!params || !norm) return ADM1_E_NULL;
@@ -450,10 +458,12 @@ int adm1_surrogate_set_weights(adm1_surrogate* s, const float* params, const adm
     rc = hip_rc(repack(s, nullptr));
     if (rc) return rc;
     return hip_rc(hipDeviceSynchronize());
+} catch (...) {
+    return ADM1_E_NOMEM;
 }
 
 int adm1_surrogate_get_weights(adm1_surrogate* s, float* params, adm1_mlp_norm* norm)
-{
+try {
     int rc = check_surrogate(s);
     if (rc) return rc;
     if (params) {
@@ -472,10 +482,12 @@ int adm1_surrogate_get_weights(adm1_surrogate* s, float* params, adm1_mlp_norm* 
     }
     if (norm) *norm = s->host_norm;
     return ADM1_OK;
+} catch (...) {
+    return ADM1_E_NOMEM;
 }
 
 int adm1_surrogate_get_grads(adm1_surrogate* s, float* grads)
-{
+try {
     int rc = check_surrogate(s);
     if (rc) return rc;
     if (!grads) return ADM1_E_NULL;
@@ -492,6 +504,8 @@ int adm1_surrogate_get_grads(adm1_surrogate* s, float* grads)
         for (int c = 0; c < kMlpDimOut[l]; ++c) *dst++ = pad[(size_t)(mlp_b_offset(l) + c)];
     }
     return ADM1_OK;
+} catch (...) {
+    return ADM1_E_NOMEM;
 }
 
 int adm1_surrogate_featurize(adm1_surrogate* s, const double* state, int64_t ld,
