@@ -81,7 +81,7 @@ def parse():
                     help="fixed path: coupling interval in seconds (the paper's Dt)")
     ap.add_argument("--substeps", type=int, default=10,
                     help="fixed path: explicit steps per interval (the paper's ten)")
-    ap.add_argument("--train-epochs", type=int, default=24)
+    ap.add_argument("--train-epochs", type=int, default=96)
     ap.add_argument("--gate-ion", type=float, default=1e-2,
                     help="surrogate gate: tolerance of the proposed ions and S_h2")
     ap.add_argument("--gate-closure", type=float, default=5e-4,
