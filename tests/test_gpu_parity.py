@@ -121,6 +121,21 @@ def test_step_parity_cstr(torch_cuda, orc, variant):
     assert worst <= PARITY_TOL
 
 
+@pytest.mark.parametrize("n", [1, 31, 33, 65])
+def test_step_parity_tiny_and_ragged(torch_cuda, orc, n):
+    """Counts that leave the persistent two-lanes-per-particle kernel with a
+    single particle, a part-filled wave (32 particles per wave) or one
+    particle past a full wave; two intervals (cold, then warm)."""
+    w = W.cstr_population(n, seed=20 + n)
+    ctx = make_ctx(w.ld)
+    worst, xg, xo, stg, sto, cg, co = run_side_by_side(ctx, orc, w, steps=2)
+    print(f"n={n}: parity {worst:.3e}")
+    assert (stg & 0x7F == 0).all() and (sto & 0x7F == 0).all()
+    assert worst <= PARITY_TOL
+    # columns past n are untouched
+    assert np.array_equal(xg[:, n:], w.X[:, n:])
+
+
 def test_step_parity_cstr_full_day(torch_cuda, orc):
     """The whole CSTR population: 256 particles, 96 coupling intervals of
     1/96 d (one simulated day), parity checked at every interval end."""
