@@ -7,6 +7,10 @@
  * state obeys the mass balance of eq. 2 with the standard ADM1 rates
  * (sec. 2.2) and inhibition forms (eqs. 3-6); S_H+ and S_h2 are algebraic,
  * fixed by the charge balance (eq. 7) and the hydrogen balance (eq. 8).
+ * Around that step: the paper's own fixed-step explicit scheme (sec. 4.3),
+ * the coupling driver between intervals (advection, inlet feed mask,
+ * diffusion between particles), binary particle snapshots, and a learned
+ * surrogate of the step with an exact fallback.
  *
  * Conventions common to every call
  *   - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA
@@ -217,10 +221,11 @@ typedef struct adm1_grid adm1_grid;
 
 /* Allocate a neighbour grid for up to n_max particles (cell arrays, the
  * particle order and copies in cell order: about 150 B per particle and 8 B
- * per cell).  ADM1_E_OPTS if a parameter is not positive and finite or the
+ * per cell).  Synchronous.  ADM1_E_OPTS if a parameter is not positive and finite or the
  * grid (cells of edge h over the box) would exceed 2^26 cells; ADM1_E_SIZE
  * for n_max outside 1..2^31-1. */
 int adm1_grid_create(const adm1_diffusion *d, int64_t n_max, adm1_grid **out);
+/* Free a grid.  Synchronous.  NULL is a no-op. */
 void adm1_grid_destroy(adm1_grid *g);
 
 /* Diffuse the soluble entries of particles 0..n-1 over dt_days in
