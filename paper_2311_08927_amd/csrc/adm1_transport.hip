@@ -27,37 +27,39 @@ namespace {
 struct Field {
     float cos_wh, sin_wh;  // turn of one substep
     float R, H;
-    float a[ADM1_FLOW_MODES];
-    int nmodes;
+    float kz;              // pi / H
+    // per mode k (1-based): a_k (axial) and a_k k pi / H (radial), so the
+    // velocity is u_r/r = -(R^2 - r^2) sum_k rad_k cos(k kz z),
+    // u_z = (2 R^2 - 4 r^2) sum_k ax_k sin(k kz z)
+    float ax[ADM1_FLOW_MODES];
+    float rad[ADM1_FLOW_MODES];
 };
 
-// Meridional velocity (the rotation is applied exactly, outside RK4).
+// Meridional velocity (the rotation is applied exactly, outside RK4) of NM
+// modes.  sin and cos of k kz z come from those of kz z by angle addition:
+// one transcendental evaluation per velocity, on the hardware sine/cosine
+// (argument in [0, pi]).
+template <int NM>
 __device__ __forceinline__ void velocity(const Field& F, float x, float y, float z, float& ux,
                                          float& uy, float& uz)
 {
     const float r2 = x * x + y * y;
     const float R2 = F.R * F.R;
-    const float kz = 3.14159265358979f / F.H;
-    float radial = 0.0f, axial = 0.0f;  // u_r / r and u_z
-    // sin and cos of (k+1) kz z from those of kz z by angle addition: one
-    // transcendental evaluation per velocity instead of one per mode, and
-    // that one on the hardware sine/cosine (argument in [0, pi]; the
-    // displacement over an interval stays within a few micrometres of the
-    // FP64 reference integration)
-    float s1, c1;
-    __sincosf(kz * z, &s1, &c1);
-    float s = s1, c = c1;
-    for (int k = 0; k < F.nmodes; ++k) {
-        const float kk = (float)(k + 1) * kz;
-        radial -= F.a[k] * (R2 - r2) * kk * c;
-        axial += F.a[k] * (2.0f * R2 - 4.0f * r2) * s;
+    float s1 = 0.0f, c1 = 1.0f;
+    if (NM > 0) __sincosf(F.kz * z, &s1, &c1);
+    float s = s1, c = c1, sc = 0.0f, ss = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        sc = fmaf(F.rad[k], c, sc);
+        ss = fmaf(F.ax[k], s, ss);
         const float sn = fmaf(s, c1, c * s1);
         c = fmaf(c, c1, -s * s1);
         s = sn;
     }
+    const float radial = -(R2 - r2) * sc;  // u_r / r
     ux = radial * x;
     uy = radial * y;
-    uz = axial;
+    uz = (2.0f * R2 - 4.0f * r2) * ss;
 }
 
 __device__ __forceinline__ void clamp_tank(const Field& F, float& x, float& y, float& z)
@@ -71,6 +73,7 @@ __device__ __forceinline__ void clamp_tank(const Field& F, float& x, float& y, f
     z = fminf(fmaxf(z, 0.0f), F.H);
 }
 
+template <int NM>
 __global__ void __launch_bounds__(256) k_advect(float* pos, int64_t ld, int64_t n, Field F,
                                                 float h, int nsub)
 {
@@ -79,10 +82,10 @@ __global__ void __launch_bounds__(256) k_advect(float* pos, int64_t ld, int64_t 
     float x = pos[i], y = pos[ld + i], z = pos[2 * ld + i];
     for (int s = 0; s < nsub; ++s) {
         float k1x, k1y, k1z, k2x, k2y, k2z, k3x, k3y, k3z, k4x, k4y, k4z;
-        velocity(F, x, y, z, k1x, k1y, k1z);
-        velocity(F, x + 0.5f * h * k1x, y + 0.5f * h * k1y, z + 0.5f * h * k1z, k2x, k2y, k2z);
-        velocity(F, x + 0.5f * h * k2x, y + 0.5f * h * k2y, z + 0.5f * h * k2z, k3x, k3y, k3z);
-        velocity(F, x + h * k3x, y + h * k3y, z + h * k3z, k4x, k4y, k4z);
+        velocity<NM>(F, x, y, z, k1x, k1y, k1z);
+        velocity<NM>(F, x + 0.5f * h * k1x, y + 0.5f * h * k1y, z + 0.5f * h * k1z, k2x, k2y, k2z);
+        velocity<NM>(F, x + 0.5f * h * k2x, y + 0.5f * h * k2y, z + 0.5f * h * k2z, k3x, k3y, k3z);
+        velocity<NM>(F, x + h * k3x, y + h * k3y, z + h * k3z, k4x, k4y, k4z);
         x += h * (1.0f / 6.0f) * (k1x + 2.0f * k2x + 2.0f * k3x + k4x);
         y += h * (1.0f / 6.0f) * (k1y + 2.0f * k2y + 2.0f * k3y + k4y);
         z += h * (1.0f / 6.0f) * (k1z + 2.0f * k2z + 2.0f * k3z + k4z);
@@ -145,11 +148,35 @@ int adm1_advect(float* pos, int64_t ld, int64_t n, const adm1_flow* flow, double
     F.sin_wh = (float)std::sin(wh);
     F.R = (float)flow->R;
     F.H = (float)flow->H;
-    F.nmodes = flow->nmodes;
-    for (int k = 0; k < ADM1_FLOW_MODES; ++k) F.a[k] = k < flow->nmodes ? (float)flow->a[k] : 0.f;
+    const double kz = 3.14159265358979323846 / flow->H;
+    F.kz = (float)kz;
+    for (int k = 0; k < ADM1_FLOW_MODES; ++k) {
+        const double a = k < flow->nmodes ? flow->a[k] : 0.0;
+        F.ax[k] = (float)a;
+        F.rad[k] = (float)(a * (k + 1) * kz);
+    }
     const unsigned grid = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(adm1::k_advect, dim3(grid), dim3(256), 0, (hipStream_t)stream, pos, ld,
-                       n, F, (float)(dt_seconds / substeps), (int)substeps);
+    const float h = (float)(dt_seconds / substeps);
+    hipStream_t s = (hipStream_t)stream;
+    switch (flow->nmodes) {
+#define ADM1_ADVECT_CASE(M)                                                                  \
+    case M:                                                                                  \
+        hipLaunchKernelGGL(adm1::k_advect<M>, dim3(grid), dim3(256), 0, s, pos, ld, n, F, h, \
+                           (int)substeps);                                                   \
+        break;
+        ADM1_ADVECT_CASE(0)
+        ADM1_ADVECT_CASE(1)
+        ADM1_ADVECT_CASE(2)
+        ADM1_ADVECT_CASE(3)
+        ADM1_ADVECT_CASE(4)
+        ADM1_ADVECT_CASE(5)
+        ADM1_ADVECT_CASE(6)
+        ADM1_ADVECT_CASE(7)
+        ADM1_ADVECT_CASE(8)
+#undef ADM1_ADVECT_CASE
+    default:
+        return ADM1_E_OPTS;
+    }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? ADM1_OK : (int)e;
 }
