@@ -220,7 +220,7 @@ typedef struct adm1_diffusion {
 typedef struct adm1_grid adm1_grid;
 
 /* Allocate a neighbour grid for up to n_max particles (cell arrays, the
- * particle order and copies in cell order: about 150 B per particle and 8 B
+ * particle order and copies in cell order: about 280 B per particle and 8 B
  * per cell).  Synchronous.  ADM1_E_OPTS if a parameter is not positive and finite or the
  * grid (cells of edge h over the box) would exceed 2^26 cells; ADM1_E_SIZE
  * for n_max outside 1..2^31-1. */

@@ -19,12 +19,17 @@
 //   k_grid_place   -- scatter of the particle indices into cell order;
 //   k_grid_sort    -- one thread per cell sorts its indices ascending, so the
 //                     order, and with it every sum, is the same run to run;
-//   k_gather_pos   -- positions in cell order, one float4 per particle;
-// then per substep k_gather_c copies the soluble entries into cell order
-// (one 128-byte row of kCRow doubles per particle) and k_diffuse, one thread
-// per particle in cell order (neighbouring threads read the same cells),
-// sums over those cells (25 index ranges: the five cells of a row along x
-// are consecutive) and adds the Euler update to the state.  A
+//   k_gather_pos   -- positions in cell order, one float4 per particle, and
+//                     the inverse permutation (each particle's slot);
+//   k_gather_c     -- the soluble entries into cell order, one 128-byte row
+//                     of kCRow doubles per particle (state read coalesced in
+//                     particle order, rows written to the particles' slots);
+// then per substep k_diffuse, one thread per particle in cell order
+// (neighbouring threads read the same cells), sums over those cells (25
+// index ranges: the five cells of a row along x are consecutive) and writes
+// the Euler-updated row into a second buffer; the two buffers swap between
+// substeps, and k_scatter_c writes the last rows back to the state in
+// particle order (coalesced).  A
 // candidate is first tested in FP32 against a slightly enlarged radius; the
 // FP64 test then decides, so the neighbour sets are those of an FP64
 // distance test.  Every launch is bounded by n or by the cell count; indices
@@ -34,6 +39,7 @@
 
 #include <cmath>
 #include <new>
+#include <utility>
 
 #include "adm1.h"
 
@@ -203,24 +209,38 @@ __global__ void __launch_bounds__(256) k_grid_sort(const int32_t* __restrict__ s
 
 __global__ void __launch_bounds__(256) k_gather_pos(const int32_t* __restrict__ sorted,
                                                     const float* __restrict__ pos, int64_t ld,
-                                                    int64_t n, float4* __restrict__ spos)
+                                                    int64_t n, float4* __restrict__ spos,
+                                                    int32_t* __restrict__ slot)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = sorted[s];
     spos[s] = float4{pos[i], pos[ld + i], pos[2 * ld + i], 0.0f};
+    slot[i] = (int32_t)s;
 }
 
-__global__ void __launch_bounds__(256) k_gather_c(const int32_t* __restrict__ sorted,
+// Particle order: coalesced reads of the state, one row write per particle.
+__global__ void __launch_bounds__(256) k_gather_c(const int32_t* __restrict__ slot,
                                                   const double* __restrict__ state, int64_t ld,
                                                   int64_t n, double* __restrict__ sc)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int64_t i = sorted[s];
-    double* row = sc + s * kCRow;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double* row = sc + (int64_t)slot[i] * kCRow;
 #pragma unroll
     for (int k = 0; k < kDiffRows; ++k) row[k] = state[diff_row(k) * ld + i];
+}
+
+// Particle order: one row read per particle, coalesced writes of the state.
+__global__ void __launch_bounds__(256) k_scatter_c(const int32_t* __restrict__ slot,
+                                                   const double* __restrict__ sc, int64_t n,
+                                                   double* __restrict__ state, int64_t ld)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* row = sc + (int64_t)slot[i] * kCRow;
+#pragma unroll
+    for (int k = 0; k < kDiffRows; ++k) state[diff_row(k) * ld + i] = row[k];
 }
 
 struct DiffArgs {
@@ -228,10 +248,9 @@ struct DiffArgs {
     const int32_t* start;
     const int32_t* sorted;
     const float4* spos;
-    const double* sc;  // [n_max][kCRow]
+    const double* sc;  // [n_max][kCRow] rows in cell order, read
+    double* out;       // [n_max][kCRow] updated rows, written
     int64_t n;
-    double* state;
-    int64_t ld;
     float h2x4_pre;  // (2h)^2 (1 + 1e-4): FP32 prefilter, never below the FP64 test
     double h2x4;     // (2h)^2
     double inv_h;
@@ -286,11 +305,10 @@ __global__ void __launch_bounds__(256) k_diffuse(DiffArgs a)
             }
         }
     }
-    const int64_t id = a.sorted[s];
+    double* row = a.out + s * kCRow;
 #pragma unroll
-    for (int k = 0; k < kDiffRows; ++k)
-        a.state[diff_row(k) * a.ld + id] = fma(a.scale, acc[k], cs[k]);
-    if (a.neighbours) a.neighbours[id] = cnt;
+    for (int k = 0; k < kDiffRows; ++k) row[k] = fma(a.scale, acc[k], cs[k]);
+    if (a.neighbours) a.neighbours[a.sorted[s]] = cnt;
 }
 
 bool is_dev(const void* p)
@@ -314,9 +332,9 @@ struct adm1_grid {
     adm1_diffusion d;
     adm1::GridGeom g;
     int64_t n_max, ncell, nblk;
-    int32_t *cell, *count, *start, *sorted, *bsum;
+    int32_t *cell, *count, *start, *sorted, *bsum, *slot;
     float4* spos;
-    double* sc;
+    double *sc, *sc2;
 };
 
 extern "C" {
@@ -350,16 +368,18 @@ int adm1_grid_create(const adm1_diffusion* d, int64_t n_max, adm1_grid** out)
     p->n_max = n_max;
     p->ncell = (int64_t)cells;
     p->nblk = (p->ncell + adm1::kScanChunk - 1) / adm1::kScanChunk;
-    p->cell = p->count = p->start = p->sorted = p->bsum = nullptr;
+    p->cell = p->count = p->start = p->sorted = p->bsum = p->slot = nullptr;
     p->spos = nullptr;
-    p->sc = nullptr;
+    p->sc = p->sc2 = nullptr;
     bool ok = hipMalloc((void**)&p->cell, n_max * sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void**)&p->sorted, n_max * sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void**)&p->count, p->ncell * sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void**)&p->start, (p->ncell + 1) * sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void**)&p->bsum, p->nblk * sizeof(int32_t)) == hipSuccess &&
               hipMalloc((void**)&p->spos, n_max * sizeof(float4)) == hipSuccess &&
-              hipMalloc((void**)&p->sc, adm1::kCRow * n_max * sizeof(double)) == hipSuccess;
+              hipMalloc((void**)&p->slot, n_max * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc((void**)&p->sc, adm1::kCRow * n_max * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&p->sc2, adm1::kCRow * n_max * sizeof(double)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         adm1_grid_destroy(p);
@@ -373,7 +393,8 @@ void adm1_grid_destroy(adm1_grid* g)
 {
     if (!g) return;
     for (void* q : {(void*)g->cell, (void*)g->count, (void*)g->start, (void*)g->sorted,
-                    (void*)g->bsum, (void*)g->spos, (void*)g->sc})
+                    (void*)g->bsum, (void*)g->slot, (void*)g->spos, (void*)g->sc,
+                    (void*)g->sc2})
         if (q) (void)hipFree(q);
     delete g;
 }
@@ -408,7 +429,9 @@ int adm1_diffuse(adm1_grid* g, double* state, int64_t ld, const float* pos, int6
     hipLaunchKernelGGL(k_grid_sort, dim3(blocks(m, 256)), dim3(256), 0, s, g->start, m,
                        g->sorted);
     hipLaunchKernelGGL(k_gather_pos, dim3(blocks(n, 256)), dim3(256), 0, s, g->sorted, pos, ld,
-                       n, g->spos);
+                       n, g->spos, g->slot);
+    hipLaunchKernelGGL(k_gather_c, dim3(blocks(n, 256)), dim3(256), 0, s, g->slot, state, ld, n,
+                       g->sc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
     const double h = g->d.h;
@@ -417,21 +440,23 @@ int adm1_diffuse(adm1_grid* g, double* state, int64_t ld, const float* pos, int6
     a.start = g->start;
     a.sorted = g->sorted;
     a.spos = g->spos;
-    a.sc = g->sc;
     a.n = n;
-    a.state = state;
-    a.ld = ld;
     a.h2x4 = 4.0 * h * h;
     a.h2x4_pre = (float)(a.h2x4 * (1.0 + 1e-4));
     a.inv_h = 1.0 / h;
     a.fcoef = -5.0 * (21.0 / (16.0 * M_PI * h * h * h)) / (h * h);
     a.scale = dt_days / substeps * 2.0 * g->d.D * g->d.V_p;
+    double* cur = g->sc;
+    double* nxt = g->sc2;
     for (int k = 0; k < substeps; ++k) {
         a.neighbours = k == 0 ? neighbours : nullptr;
-        hipLaunchKernelGGL(k_gather_c, dim3(blocks(n, 256)), dim3(256), 0, s, g->sorted, state,
-                           ld, n, g->sc);
+        a.sc = cur;
+        a.out = nxt;
         hipLaunchKernelGGL(k_diffuse, dim3(blocks(n, 256)), dim3(256), 0, s, a);
+        std::swap(cur, nxt);
     }
+    hipLaunchKernelGGL(k_scatter_c, dim3(blocks(n, 256)), dim3(256), 0, s, g->slot, cur, n,
+                       state, ld);
     e = hipGetLastError();
     return e == hipSuccess ? ADM1_OK : (int)e;
 }
