@@ -181,3 +181,48 @@ def test_queue_order_does_not_change_results(torch_cuda):
         for x, y in zip(a, b):
             assert np.array_equal(x, y, equal_nan=True)
     assert int((runs[A.ORDER_COST][-1][3] != 0).sum()) == 0
+
+
+def test_fixed_step_and_diffusion_in_a_graph(torch_cuda):
+    """adm1_step_fixed and adm1_diffuse (grid build, two substeps) captured
+    together into one graph: every replay equals the same eager calls bit for
+    bit, with unrelated GPU work and host synchronisations between replays
+    (the calls launch kernels only: no allocation, no memset)."""
+    torch = torch_cuda
+    from paper_2311_08927_amd import adm1 as A
+    n = 3000
+    w = W.cstr_population(n, seed=5)
+    ctx = make_ctx(w.ld)
+    g = np.random.default_rng(9)
+    pos_h = np.zeros((3, w.ld), dtype=np.float32)
+    pos_h[:, :n] = (g.random((3, n)) * np.array([[0.04], [0.03], [0.02]])).astype(np.float32)
+    pos = torch.from_numpy(pos_h).cuda()
+    V_p = 0.04 * 0.03 * 0.02 / n
+    grid = A.Grid(A.make_diffusion(1.3 * V_p ** (1 / 3), 1e-9 * 86400.0, V_p, [0, 0, 0],
+                                   [0.04, 0.03, 0.02]), w.ld)
+    eager, graphd = DeviceWorkload(w), DeviceWorkload(w)
+    dt_fixed, dt_diff = 0.5 / 86400.0, 600.0 / 86400.0
+
+    def calls(dw):
+        ctx.step_fixed(dw.X, dw.T, dw.D, dw.fidx, dw.S_in, dt_fixed, 10, A.FIXED_EULER, n=n,
+                       H=dw.H, status=dw.status)
+        grid.diffuse(dw.X, pos, n, dt_diff, 2)
+
+    cg = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.graph(cg, stream=s, capture_error_mode="relaxed"):
+        calls(graphd)
+    try:
+        junk = torch.zeros(1 << 20, device="cuda")
+        for k in range(4):
+            calls(eager)
+            torch.cuda.synchronize()
+            junk.add_(1.0)
+            cg.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(eager.X, graphd.X), k
+            assert torch.equal(eager.H, graphd.H), k
+            assert (graphd.status == 0).all(), k
+    finally:
+        del cg
+        grid.close()
