@@ -207,8 +207,13 @@ int adm1_step_fixed(adm1_ctx *ctx, double *state, int64_t ld, const double *temp
  * substeps.  The algebraic entries are refreshed by the next reaction step.
  * Neighbours are found on a uniform grid of cells of edge h over the box
  * [lo, hi] (particles outside it are clamped into the edge cells, which
- * stays exact, only slower).  Explicit Euler is stable for roughly
- * dt/substeps < 0.1 spacing^2 / D; the caller chooses substeps. */
+ * stays exact, only slower).  Stability of the explicit steps: the kernel
+ * factor integrates to sum_j V_p |W'/r| ~ 3.5 / h^2 for evenly spread
+ * particles, but randomly placed ones reach about twice that, so the
+ * operator's rates reach ~28 D / h^2 (Gershgorin) and a substep must stay
+ * below ~0.07 h^2 / D; use dt/substeps <= 0.05 h^2 / D (longer substeps make
+ * the concentrations of clustered particles oscillate and grow).  The
+ * caller chooses substeps. */
 typedef struct adm1_diffusion {
     double h;     /* smoothing length (m) */
     double D;     /* diffusivity of the soluble entries (m2/d) */
@@ -362,10 +367,13 @@ typedef struct adm1_flow {
 } adm1_flow;
 
 /* Move particles 0..n-1 for dt_seconds in `substeps` equal substeps: a
- * classical RK4 step of the meridional (axisymmetric) modes, then the exact
- * turn by omega h (the two commute); positions stay inside the tank (radial
- * and axial clamp).  pos: float32 [3][ld] device array (x, y, z in m), in
- * place. */
+ * classical RK4 step of the meridional (axisymmetric) modes, then the turn
+ * by omega h (the two commute), done as three area-preserving shears; a
+ * particle that crosses a boundary by rounding is reflected back inside.
+ * Positions are advanced in FP64 over all substeps and rounded to FP32 once
+ * (in FP32, increments near the axial stagnation points round away and
+ * particles collapse onto the axis).  pos: float32 [3][ld] device array
+ * (x, y, z in m), in place. */
 int adm1_advect(float *pos, int64_t ld, int64_t n, const adm1_flow *flow, double dt_seconds,
                 int32_t substeps, void *stream);
 

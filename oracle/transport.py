@@ -10,7 +10,9 @@ rotation: the flow over a substep h is the meridional flow (classical RK4)
 followed by the exact turn of the (x, y) plane by omega h.  (RK4 on the whole
 field damps the rotation by |R(i omega h)| < 1 per step, about 2 % at 12 rpm
 and h = 1 s, so particles would spiral onto the axis within one interval.)
-Particles are clamped to the tank; the feed mask marks particles in the
+A particle that crosses the wall, the bottom or the lid by rounding is
+reflected back inside (the boundary is an invariant set of the flow, so a
+particle placed on it would stay there); the feed mask marks particles in the
 inlet region z >= z_min, r <= r_max (sec. 2.3: the AD particles follow the
 fluid particles).
 """
@@ -62,8 +64,10 @@ def advect(pos, omega, R, H, a, dt_seconds, substeps):
         # solid-body rotation, exact
         x, y = c * x - s_ * y, s_ * x + c * y
         r = np.sqrt(x * x + y * y)
-        s = np.where(r > R, R / np.maximum(r, 1e-300), 1.0)
+        s = np.where(r > R, np.maximum(2.0 * R - r, 0.0) / np.maximum(r, 1e-300), 1.0)
         x, y = x * s, y * s
+        z = np.where(z < 0.0, -z, z)
+        z = np.where(z > H, 2.0 * H - z, z)
         z = np.clip(z, 0.0, H)
     return np.stack([x, y, z])
 

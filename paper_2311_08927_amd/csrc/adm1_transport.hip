@@ -9,11 +9,31 @@
 //     psi(r, z) = sum_k a_k r^2 (R^2 - r^2) sin(k pi z / H),
 //     u_r = -(1/r) dpsi/dz,  u_z = (1/r) dpsi/dr,  u_theta = Omega r,
 // which is tangent to the wall and to the bottom and top.  Positions are
-// FP32 structure-of-arrays pos[3][ld] (x, y, z in m).  The meridional part
-// (u_r, u_z) is axisymmetric and so commutes with the rotation: each substep
-// is a classical RK4 step of the meridional flow followed by the exact turn
-// of the (x, y) plane by Omega h (RK4 on the rotation itself would shrink
-// every orbit by about 2 % per 1 s substep at 12 rpm).
+// stored as FP32 structure-of-arrays pos[3][ld] (x, y, z in m) but advanced
+// in FP64 over all substeps of a call.  The meridional part (u_r, u_z) is
+// axisymmetric and so commutes with the rotation: each substep is a
+// classical RK4 step of the meridional flow followed by the turn of the
+// (x, y) plane by Omega h (RK4 on the rotation itself would shrink every
+// orbit by about 2 % per 1 s substep at 12 rpm).  The turn is three shears,
+// x -= t y, y += s x, x -= t y with t = tan(Omega h / 2), s = sin(Omega h):
+// each shear has determinant 1 whatever the rounding of t and s, so orbits
+// stay closed.  A particle that still crosses a wall or the lid by rounding
+// is reflected back inside: the boundary is an invariant set of the flow, so
+// a particle placed on it would stay there for good.
+//
+// Why FP64: the axis is invariant too, and where the meridional flow
+// converges radially onto it (an axial stagnation point z1 with u_z ~
+// c (z - z1), c > 0) a particle on the converging side leaves along the axis
+// only as fast as |z - z1| grows.  In FP32 that growth per substep falls
+// below half an ulp of z within a few tenths of a micrometre of z1 (and the
+// FP32 velocity carries rounding noise of that order), so z stops moving
+// while r keeps shrinking geometrically down to denormals; such particles
+// then collect at the next stagnation point on the axis, dozens at one
+// position after a few hour-long intervals, where the exact flow (which
+// conserves r^2 (z - z1)) keeps them apart.  In FP64 the band of lost
+// increments is ~1e-17 m wide and no particle falls into it.  Non-packed
+// FP32 and FP64 fused multiply-adds issue at the same rate on CDNA, so the
+// price is mostly the FP64 sine and cosine.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,78 +45,86 @@ namespace adm1 {
 namespace {
 
 struct Field {
-    float cos_wh, sin_wh;  // turn of one substep
-    float R, H;
-    float kz;              // pi / H
+    double tan_half, sin_wh;  // turn of one substep as three shears
+    double R, H;
+    double kz;  // pi / H
     // per mode k (1-based): a_k (axial) and a_k k pi / H (radial), so the
     // velocity is u_r/r = -(R^2 - r^2) sum_k rad_k cos(k kz z),
     // u_z = (2 R^2 - 4 r^2) sum_k ax_k sin(k kz z)
-    float ax[ADM1_FLOW_MODES];
-    float rad[ADM1_FLOW_MODES];
+    double ax[ADM1_FLOW_MODES];
+    double rad[ADM1_FLOW_MODES];
 };
 
 // Meridional velocity (the rotation is applied exactly, outside RK4) of NM
-// modes.  sin and cos of k kz z come from those of kz z by angle addition:
-// one transcendental evaluation per velocity, on the hardware sine/cosine
-// (argument in [0, pi]).
+// modes, as u_r / r and u_z.  sin and cos of k kz z come from those of kz z
+// by angle addition: one sine/cosine evaluation per velocity.
 template <int NM>
-__device__ __forceinline__ void velocity(const Field& F, float x, float y, float z, float& ux,
-                                         float& uy, float& uz)
+__device__ __forceinline__ void velocity(const Field& F, double x, double y, double z,
+                                         double& g, double& uz)
 {
-    const float r2 = x * x + y * y;
-    const float R2 = F.R * F.R;
-    float s1 = 0.0f, c1 = 1.0f;
-    if (NM > 0) __sincosf(F.kz * z, &s1, &c1);
-    float s = s1, c = c1, sc = 0.0f, ss = 0.0f;
+    const double r2 = x * x + y * y;
+    const double R2 = F.R * F.R;
+    double s1 = 0.0, c1 = 1.0;
+    if (NM > 0) sincos(F.kz * z, &s1, &c1);
+    double s = s1, c = c1, sc = 0.0, ss = 0.0;
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
-        sc = fmaf(F.rad[k], c, sc);
-        ss = fmaf(F.ax[k], s, ss);
-        const float sn = fmaf(s, c1, c * s1);
-        c = fmaf(c, c1, -s * s1);
+        sc = fma(F.rad[k], c, sc);
+        ss = fma(F.ax[k], s, ss);
+        const double sn = fma(s, c1, c * s1);
+        c = fma(c, c1, -s * s1);
         s = sn;
     }
-    const float radial = -(R2 - r2) * sc;  // u_r / r
-    ux = radial * x;
-    uy = radial * y;
-    uz = (2.0f * R2 - 4.0f * r2) * ss;
+    g = -(R2 - r2) * sc;
+    uz = (2.0 * R2 - 4.0 * r2) * ss;
 }
 
-__device__ __forceinline__ void clamp_tank(const Field& F, float& x, float& y, float& z)
+// Reflect a particle that crossed the wall, the bottom or the lid back into
+// the tank (then clamp, for overshoots larger than the tank).
+__device__ __forceinline__ void reflect_tank(const Field& F, double& x, double& y, double& z)
 {
-    const float r2 = x * x + y * y;
+    const double r2 = x * x + y * y;
     if (r2 > F.R * F.R) {
-        const float s = F.R * rsqrtf(r2);
-        x *= s;
-        y *= s;
+        const double r = sqrt(r2);
+        const double f = fmax(2.0 * F.R - r, 0.0) / r;
+        x *= f;
+        y *= f;
     }
-    z = fminf(fmaxf(z, 0.0f), F.H);
+    if (z < 0.0) z = -z;
+    if (z > F.H) z = 2.0 * F.H - z;
+    z = fmin(fmax(z, 0.0), F.H);
 }
 
 template <int NM>
 __global__ void __launch_bounds__(256) k_advect(float* pos, int64_t ld, int64_t n, Field F,
-                                                float h, int nsub)
+                                                double h, int nsub)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float x = pos[i], y = pos[ld + i], z = pos[2 * ld + i];
+    double x = pos[i], y = pos[ld + i], z = pos[2 * ld + i];
+    const double hh = 0.5 * h, h6 = h / 6.0;
     for (int s = 0; s < nsub; ++s) {
-        float k1x, k1y, k1z, k2x, k2y, k2z, k3x, k3y, k3z, k4x, k4y, k4z;
-        velocity<NM>(F, x, y, z, k1x, k1y, k1z);
-        velocity<NM>(F, x + 0.5f * h * k1x, y + 0.5f * h * k1y, z + 0.5f * h * k1z, k2x, k2y, k2z);
-        velocity<NM>(F, x + 0.5f * h * k2x, y + 0.5f * h * k2y, z + 0.5f * h * k2z, k3x, k3y, k3z);
-        velocity<NM>(F, x + h * k3x, y + h * k3y, z + h * k3z, k4x, k4y, k4z);
-        x += h * (1.0f / 6.0f) * (k1x + 2.0f * k2x + 2.0f * k3x + k4x);
-        y += h * (1.0f / 6.0f) * (k1y + 2.0f * k2y + 2.0f * k3y + k4y);
-        z += h * (1.0f / 6.0f) * (k1z + 2.0f * k2z + 2.0f * k3z + k4z);
-        const float xr = F.cos_wh * x - F.sin_wh * y;
-        y = F.sin_wh * x + F.cos_wh * y;
-        x = xr;
-        clamp_tank(F, x, y, z);
+        // u_x = g x and u_y = g y: every stage scales x and y alike
+        double g1, g2, g3, g4, w1, w2, w3, w4;
+        velocity<NM>(F, x, y, z, g1, w1);
+        const double m2 = fma(hh, g1, 1.0);
+        velocity<NM>(F, m2 * x, m2 * y, fma(hh, w1, z), g2, w2);
+        const double m3 = fma(hh * g2, m2, 1.0);
+        velocity<NM>(F, m3 * x, m3 * y, fma(hh, w2, z), g3, w3);
+        const double m4 = fma(h * g3, m3, 1.0);
+        velocity<NM>(F, m4 * x, m4 * y, fma(h, w3, z), g4, w4);
+        const double m = fma(h6, g1 + 2.0 * g2 * m2 + 2.0 * g3 * m3 + g4 * m4, 1.0);
+        x *= m;
+        y *= m;
+        z = fma(h6, w1 + 2.0 * w2 + 2.0 * w3 + w4, z);
+        x = fma(-F.tan_half, y, x);
+        y = fma(F.sin_wh, x, y);
+        x = fma(-F.tan_half, y, x);
+        reflect_tank(F, x, y, z);
     }
-    pos[i] = x;
-    pos[ld + i] = y;
-    pos[2 * ld + i] = z;
+    pos[i] = (float)x;
+    pos[ld + i] = (float)y;
+    pos[2 * ld + i] = (float)z;
 }
 
 // Inlet membership at the start of the interval: z >= z_min and r <= r_max.
@@ -144,19 +172,19 @@ int adm1_advect(float* pos, int64_t ld, int64_t n, const adm1_flow* flow, double
     if (n == 0) return ADM1_OK;
     adm1::Field F;
     const double wh = flow->omega * (dt_seconds / substeps);
-    F.cos_wh = (float)std::cos(wh);
-    F.sin_wh = (float)std::sin(wh);
-    F.R = (float)flow->R;
-    F.H = (float)flow->H;
+    F.tan_half = std::tan(0.5 * wh);
+    F.sin_wh = std::sin(wh);
+    F.R = flow->R;
+    F.H = flow->H;
     const double kz = 3.14159265358979323846 / flow->H;
-    F.kz = (float)kz;
+    F.kz = kz;
     for (int k = 0; k < ADM1_FLOW_MODES; ++k) {
         const double a = k < flow->nmodes ? flow->a[k] : 0.0;
-        F.ax[k] = (float)a;
-        F.rad[k] = (float)(a * (k + 1) * kz);
+        F.ax[k] = a;
+        F.rad[k] = a * (k + 1) * kz;
     }
     const unsigned grid = (unsigned)((n + 255) / 256);
-    const float h = (float)(dt_seconds / substeps);
+    const double h = dt_seconds / substeps;
     hipStream_t s = (hipStream_t)stream;
     switch (flow->nmodes) {
 #define ADM1_ADVECT_CASE(M)                                                                  \
