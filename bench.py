@@ -497,7 +497,7 @@ def surrogate_main(args):
     for k in range(args.burn_in):
         mask()
         ctx.step(X, T, D, fidx, S_in, wd.dt, n=wd.n, H=H, hlast=hl, status=status)
-        A.adm1_advect(pos, wd.ld, wd.n, flow, dt_s, int(dt_s))
+        A.adm1_advect(pos, wd.ld, wd.n, flow, dt_s, W.advect_substeps(dt_s))
     torch.cuda.synchronize()
     X0, H0, hl0, pos0 = X.clone(), H.clone(), hl.clone(), pos.clone()
     gate = S.adm1_gate(5.0, args.gate_ion, args.gate_closure)
@@ -565,7 +565,7 @@ def surrogate_main(args):
             tot[path][k].copy_(tot_g)
             if path == "sur":
                 fb[k:k + 1].copy_(fb_g)
-            A.adm1_advect(pos, wd.ld, wd.n, flow, dt_s, int(dt_s))
+            A.adm1_advect(pos, wd.ld, wd.n, flow, dt_s, W.advect_substeps(dt_s))
             log(f"# {path} step {k} enqueued")
         torch.cuda.synchronize()
         ms[path] = sum(e0.elapsed_time(e1) for e0, e1 in ev)

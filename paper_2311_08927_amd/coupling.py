@@ -4,7 +4,7 @@ Between two coupling steps every particle is displaced by the flow (it
 follows its fluid particle, sec. 2.3), the inlet feed mask is rebuilt from
 the new positions, and (optionally) the soluble entries diffuse between
 neighbouring particles.  `python -m paper_2311_08927_amd.coupling` times
-adm1_advect (one coupling interval of 1/96 d in 1 s RK4 substeps),
+adm1_advect (one coupling interval of 1/96 d in the field's 0.25 s substeps),
 adm1_feed_mask and adm1_diffuse (grid build plus one explicit step of
 molecular diffusion, h = 1.3 x the mean particle spacing) on the field's
 seeded positions and states with HIP events on the launching stream, and
@@ -34,7 +34,7 @@ def main():
     D = torch.empty(n, dtype=torch.float64, device="cuda")
     fidx = torch.empty(n, dtype=torch.int32, device="cuda")
     dt_s = W.DT * 86400.0
-    sub = int(round(dt_s))
+    sub = W.advect_substeps(dt_s)
     stream = torch.cuda.current_stream()
 
     def timed(fn):

@@ -96,7 +96,7 @@ def main():
 
     def D_at(s):
         if s > 0:
-            A.adm1_advect(pos, w.ld, w.n, flow, dt_s, int(dt_s))
+            A.adm1_advect(pos, w.ld, w.n, flow, dt_s, W.advect_substeps(dt_s))
         mask()
         print(f"# step {s}", file=sys.stderr, flush=True)
         return D

@@ -300,7 +300,7 @@ def integrate_field_states(ctx, w: W.Workload, steps: int):
         D = torch.empty(w.n, dtype=torch.float64, device=dev)
         A.adm1_feed_mask(pos, w.ld, w.n, W.INLET_Z, W.INLET_R, 1.0, 1, 0, D, fidx)
         ctx.step(X, T, D, fidx, S_in, w.dt, n=w.n, H=H, hlast=hl, status=status)
-        A.adm1_advect(pos, w.ld, w.n, flow, dt_s, int(dt_s))
+        A.adm1_advect(pos, w.ld, w.n, flow, dt_s, W.advect_substeps(dt_s))
         states.append(X.clone())
         Ds.append(D)
         ok.append(status == 0)

@@ -84,3 +84,42 @@ def test_neighbour_counts_on_a_lattice():
     cnt = OD.neighbour_counts(P, 0.75 * d)
     centre = int(np.argmin((P ** 2).sum(axis=0)))
     assert cnt[centre] == 18
+
+
+def test_stability_bound_of_the_explicit_step():
+    """The documented bound: sum_j V_p |W'/r| integrates to 3.5 / h^2, so on
+    evenly spread particles the operator's rates stay below 14 D / h^2 and
+    explicit Euler is stable for dt <= h^2 / (7 D).  On a lattice, a
+    checkerboard perturbation (the fastest mode) decays with substeps of
+    0.1 h^2 / D and grows with substeps of h^2 / D."""
+    h = 0.5
+    r = np.linspace(0.0, 2.0 * h, 200_001)
+    integral = np.trapezoid(4.0 * math.pi * r ** 2 * -OD.kernel_f(r, h), r)
+    assert abs(integral * h * h - 3.5) < 1e-8
+    d = 1.0
+    P = lattice(5, d)
+    hl, D, Vp = 1.5 * d, 1.0, d ** 3
+    chk = np.where((np.round(P / d).sum(axis=0) % 2) == 0, 1.0, -1.0)
+    inner = np.all(np.abs(P) <= 2 * d, axis=0)
+    state = np.zeros((35, P.shape[1]))
+    state[OD.DIFFUSING[0]] = 1.0 + 0.01 * chk
+    amp0 = np.abs(state[OD.DIFFUSING[0], inner] - 1.0).max()
+    ok = OD.diffuse(state, P, P.shape[1], hl, Vp, D, 0.1 * hl * hl / D, 1)
+    bad = OD.diffuse(state, P, P.shape[1], hl, Vp, D, 1.0 * hl * hl / D, 1)
+    assert np.abs(ok[OD.DIFFUSING[0], inner] - 1.0).max() < amp0
+    assert np.abs(bad[OD.DIFFUSING[0], inner] - 1.0).max() > amp0
+    # randomly placed particles: interior row sums average the even-spread
+    # 3.5 / h^2 but reach about twice it, hence the 0.05 h^2 / D substep
+    g = np.random.default_rng(1)
+    n, L = 4000, np.array([0.04, 0.03, 0.02])
+    Q = g.random((3, n)) * L[:, None]
+    Vq = np.prod(L) / n
+    hq = 1.3 * Vq ** (1 / 3)
+    rows = np.zeros(n)
+    for i0 in range(0, n, 500):
+        rr, mask = OD._pairs(Q, i0, min(n, i0 + 500), hq)
+        rows[i0:i0 + 500] = np.where(mask, -OD.kernel_f(rr, hq), 0.0).sum(axis=1)
+    rows *= Vq * hq * hq
+    interior = np.all((Q > 2 * hq) & (Q < L[:, None] - 2 * hq), axis=0)
+    assert abs(rows[interior].mean() / 3.5 - 1.0) < 0.05
+    assert 1.4 < rows[interior].max() / 3.5 < 2.2
