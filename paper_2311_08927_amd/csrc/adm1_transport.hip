@@ -31,9 +31,9 @@
 // then collect at the next stagnation point on the axis, dozens at one
 // position after a few hour-long intervals, where the exact flow (which
 // conserves r^2 (z - z1)) keeps them apart.  In FP64 the band of lost
-// increments is ~1e-17 m wide and no particle falls into it.  Non-packed
-// FP32 and FP64 fused multiply-adds issue at the same rate on CDNA, so the
-// price is mostly the FP64 sine and cosine.
+// increments is ~1e-17 m wide and no particle falls into it.  The price is
+// the FP64 issue rate (half the FP32 vector rate) and the FP64 sine and
+// cosine: about 2.9x the FP32 kernel per particle-substep.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
