@@ -32,8 +32,8 @@
 // position after a few hour-long intervals, where the exact flow (which
 // conserves r^2 (z - z1)) keeps them apart.  In FP64 the band of lost
 // increments is ~1e-17 m wide and no particle falls into it.  The price is
-// the FP64 issue rate (half the FP32 vector rate) and the FP64 sine and
-// cosine: about 2.9x the FP32 kernel per particle-substep.
+// the FP64 issue rate (half the FP32 vector rate); one FP64 sine and cosine
+// per substep, the RK4 stages turning that angle by their short offsets.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -56,16 +56,14 @@ struct Field {
 };
 
 // Meridional velocity (the rotation is applied exactly, outside RK4) of NM
-// modes, as u_r / r and u_z.  sin and cos of k kz z come from those of kz z
-// by angle addition: one sine/cosine evaluation per velocity.
+// modes at sin and cos of kz z given, as u_r / r and u_z.  sin and cos of
+// k kz z come from those of kz z by angle addition.
 template <int NM>
-__device__ __forceinline__ void velocity(const Field& F, double x, double y, double z,
+__device__ __forceinline__ void velocity(const Field& F, double x, double y, double s1, double c1,
                                          double& g, double& uz)
 {
     const double r2 = x * x + y * y;
     const double R2 = F.R * F.R;
-    double s1 = 0.0, c1 = 1.0;
-    if (NM > 0) sincos(F.kz * z, &s1, &c1);
     double s = s1, c = c1, sc = 0.0, ss = 0.0;
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
@@ -77,6 +75,36 @@ __device__ __forceinline__ void velocity(const Field& F, double x, double y, dou
     }
     g = -(R2 - r2) * sc;
     uz = (2.0 * R2 - 4.0 * r2) * ss;
+}
+
+// sin and cos of (theta + e) from those of theta.  An RK4 stage sits a short
+// way from the substep's start (|e| = kz |dz| is ~0.1 rad at the field's
+// speeds), so sin e and cos e come from their Taylor series through e^11 and
+// e^12 (truncation below 1e-17 for |e| <= 0.25); longer offsets take the
+// library sine and cosine.
+__device__ __forceinline__ void turn_angle(double sb, double cb, double e, double& s, double& c)
+{
+    double se, ce;
+    if (fabs(e) <= 0.25) {
+        const double e2 = e * e;
+        double p = -1.0 / 39916800.0;
+        p = fma(p, e2, 1.0 / 362880.0);
+        p = fma(p, e2, -1.0 / 5040.0);
+        p = fma(p, e2, 1.0 / 120.0);
+        p = fma(p, e2, -1.0 / 6.0);
+        se = fma(e * e2, p, e);
+        double q = 1.0 / 479001600.0;
+        q = fma(q, e2, -1.0 / 3628800.0);
+        q = fma(q, e2, 1.0 / 40320.0);
+        q = fma(q, e2, -1.0 / 720.0);
+        q = fma(q, e2, 1.0 / 24.0);
+        q = fma(q, e2, -0.5);
+        ce = fma(e2, q, 1.0);
+    } else {
+        sincos(e, &se, &ce);
+    }
+    s = fma(sb, ce, cb * se);
+    c = fma(cb, ce, -sb * se);
 }
 
 // Reflect a particle that crossed the wall, the bottom or the lid back into
@@ -105,14 +133,18 @@ __global__ void __launch_bounds__(256) k_advect(float* pos, int64_t ld, int64_t 
     const double hh = 0.5 * h, h6 = h / 6.0;
     for (int s = 0; s < nsub; ++s) {
         // u_x = g x and u_y = g y: every stage scales x and y alike
-        double g1, g2, g3, g4, w1, w2, w3, w4;
-        velocity<NM>(F, x, y, z, g1, w1);
+        double g1, g2, g3, g4, w1, w2, w3, w4, sb = 0.0, cb = 1.0, st = 0.0, ct = 1.0;
+        if (NM > 0) sincos(F.kz * z, &sb, &cb);
+        velocity<NM>(F, x, y, sb, cb, g1, w1);
         const double m2 = fma(hh, g1, 1.0);
-        velocity<NM>(F, m2 * x, m2 * y, fma(hh, w1, z), g2, w2);
+        if (NM > 0) turn_angle(sb, cb, F.kz * (hh * w1), st, ct);
+        velocity<NM>(F, m2 * x, m2 * y, st, ct, g2, w2);
         const double m3 = fma(hh * g2, m2, 1.0);
-        velocity<NM>(F, m3 * x, m3 * y, fma(hh, w2, z), g3, w3);
+        if (NM > 0) turn_angle(sb, cb, F.kz * (hh * w2), st, ct);
+        velocity<NM>(F, m3 * x, m3 * y, st, ct, g3, w3);
         const double m4 = fma(h * g3, m3, 1.0);
-        velocity<NM>(F, m4 * x, m4 * y, fma(h, w3, z), g4, w4);
+        if (NM > 0) turn_angle(sb, cb, F.kz * (h * w3), st, ct);
+        velocity<NM>(F, m4 * x, m4 * y, st, ct, g4, w4);
         const double m = fma(h6, g1 + 2.0 * g2 * m2 + 2.0 * g3 * m3 + g4 * m4, 1.0);
         x *= m;
         y *= m;
