@@ -6,11 +6,12 @@ or the paper's fixed-step explicit scheme), the soluble entries optionally
 diffuse between neighbouring particles, the tank gas flows are reduced, and
 the particles move with the flow to their next positions (the seeded
 analytic field standing in for the SPH solver).  Optionally a binary
-snapshot of positions and states is written per interval.  All arrays stay
+snapshot of positions and states is written per interval, and a run can
+resume from one (`--resume`).  All arrays stay
 in HBM; only the four gas totals come back to the host.
 
     python -m paper_2311_08927_amd.chad --n 4194304 --steps 10 \\
-        [--scheme adaptive|fixed] [--diffusion 1e-9] [--snapshot-dir DIR]
+        [--scheme adaptive|fixed] [--diffusion 1e-9] [--snapshot-dir DIR] [--resume FILE]
 
 prints the time of every stage per interval and the tank methane flow.
 """
@@ -90,6 +91,34 @@ class Loop:
         stage("advection", lambda: A.adm1_advect(self.pos, self.ld, self.n, self.flow, dt_s,
                                                  W.advect_substeps(dt_s)))
 
+    def save(self, path, time_s):
+        """Write the particle positions and ADM1 states to a binary snapshot."""
+        from . import snapshot as S
+        S.adm1_snapshot_write(path, self.n, self.ld, time_s, pos=self.pos.cpu(),
+                              state=self.X.cpu())
+
+    def load(self, path):
+        """Restore positions and states from a snapshot of the same particle
+        count and return its time (s).  The per-particle warm starts (the
+        S_H+ guess of the charge-balance solve and the adaptive scheme's
+        last step size) are not part of a snapshot and restart from their
+        defaults, so a resumed run agrees with an uninterrupted one to the
+        solver tolerances, not bit for bit (positions do agree bit for
+        bit)."""
+        from . import snapshot as S
+        torch = self.torch
+        n, _, time_s = S.adm1_snapshot_info(path)
+        if n != self.n:
+            raise ValueError(f"snapshot holds {n} particles, the loop {self.n}")
+        pos_h = torch.empty(self.pos.shape, dtype=self.pos.dtype)
+        X_h = torch.empty(self.X.shape, dtype=self.X.dtype)
+        S.adm1_snapshot_read(path, self.ld, pos=pos_h, state=X_h)
+        self.pos.copy_(pos_h)
+        self.X.copy_(X_h)
+        self.H.fill_(-1.0)
+        self.hl.fill_(-1.0)
+        return time_s
+
     def close(self):
         if self.grid is not None:
             self.grid.close()
@@ -110,9 +139,12 @@ def main():
                     help="diffusivity of the soluble entries in m2/s (0: off)")
     ap.add_argument("--snapshot-dir", default="",
                     help="write positions and states after every interval")
+    ap.add_argument("--resume", default="",
+                    help="start from the positions and states of this snapshot")
     args = ap.parse_args()
     from . import snapshot as S
     loop = Loop(args.n, scheme=args.scheme, substeps=args.substeps, diffusion=args.diffusion)
+    t0_s = loop.load(args.resume) if args.resume else 0.0
     names = ["feed mask", "reaction"] + (["diffusion"] if loop.grid is not None else []) + \
         ["gas flux", "advection"]
     if args.snapshot_dir:
@@ -136,7 +168,7 @@ def main():
             torch.cuda.current_stream().synchronize()
             t0 = time.perf_counter()
             S.adm1_snapshot_write(os.path.join(args.snapshot_dir, f"chad_{k:04d}.bin"),
-                                  args.n, loop.ld, (k + 1) * loop.dt * 86400.0, pos=pos_h,
+                                  args.n, loop.ld, t0_s + (k + 1) * loop.dt * 86400.0, pos=pos_h,
                                   state=X_h)
             snap_ms = (time.perf_counter() - t0) * 1e3
             ev["snapshot"][1].record()

@@ -46,3 +46,45 @@ def test_loop_runs_and_repeats(torch_cuda, scheme):
     assert runs[0][1] == runs[1][1]
     print(f"{scheme}: tank CH4 flow per interval {[f'{v:.4e}' for v in runs[0][1]]}")
     assert all(math.isfinite(v) for v in runs[0][1])
+
+
+@pytest.mark.parametrize("scheme", ["fixed", "adaptive"])
+def test_resume_from_a_snapshot(torch_cuda, scheme, tmp_path):
+    """Two intervals, a snapshot, a fresh loop resumed from it and one more
+    interval: the same positions as three uninterrupted intervals, bit for
+    bit, and the same states to within the solver tolerances (the S_H+
+    warm starts, and the adaptive scheme's step sizes, restart from their
+    defaults)."""
+    from paper_2311_08927_amd import chad
+    from paper_2311_08927_amd import workloads as W
+    n = 8192
+
+    def make():
+        return chad.Loop(n, scheme=scheme, substeps=900, diffusion=1e-9)
+
+    ref = make()
+    for _ in range(3):
+        ref.interval()
+    a = make()
+    for _ in range(2):
+        a.interval()
+    path = str(tmp_path / "chad.bin")
+    a.save(path, 2 * a.dt * 86400.0)
+    b = make()
+    assert b.load(path) == 2 * a.dt * 86400.0
+    b.interval()
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(b.pos[:, :n], ref.pos[:, :n])
+    Xb, Xr = b.X[:, :n].cpu().numpy(), ref.X[:, :n].cpu().numpy()
+    scale = np.maximum(np.abs(Xr), 1e-4 * W.nominal()["state"][:, None])
+    err = float((np.abs(Xb - Xr) / scale).max())
+    print(f"{scheme} resume: max relative difference {err:.2e}")
+    assert err < (1e-6 if scheme == "fixed" else 1e-5)
+    for lp in (ref, a, b):
+        lp.close()
+    with pytest.raises(ValueError):
+        small = chad.Loop(4096, scheme=scheme, substeps=900)
+        try:
+            small.load(path)
+        finally:
+            small.close()
