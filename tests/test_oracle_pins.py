@@ -107,8 +107,9 @@ def test_rodas4_order_conditions(orc):
 
     assert conds(b, 4).max() < 1e-12
     assert conds(bh, 3).max() < 1e-12
-    # the solution is not of order 5 (the estimate is meaningful)
-    assert abs(b @ ai**4 - 0.2) > 1e-6 or True
+    # the embedded solution is NOT of order 4, so y1 - yhat1 is a genuine
+    # O(h^4) error estimate (an embedded order-4 solution would make it vanish)
+    assert conds(bh, 4).max() > 1e-3
 
 
 # ---------------------------------------------------------------------------
@@ -285,6 +286,12 @@ def test_inhibition_half_points(orc):
         # fully active at high pH, inhibited at low pH
         assert L.orc_inhib(2, 10 ** -(UL + 1), LL, UL) > 0.99
         assert L.orc_inhib(2, 10 ** -(LL - 1), LL, UL) < 0.01
+        # the exponent: with n = 3/(UL - LL) the Hill form is a logistic in pH
+        # that rises by 3 decades of (S_H+/K)^n between the limits, so at
+        # pH = UL it reads 1/(1 + 10^-1.5) = 0.969346 and at pH = LL
+        # 1/(1 + 10^1.5) = 0.030654 (n = 2/(UL - LL) would give 0.909, 0.091)
+        assert abs(L.orc_inhib(2, 10 ** -UL, LL, UL) - 0.9693465699682844) < 1e-12
+        assert abs(L.orc_inhib(2, 10 ** -LL, LL, UL) - 0.030653430031715604) < 1e-12
 
 
 UPTAKE = [  # process index, substrate, K_S, biomass, k_m
@@ -352,6 +359,103 @@ def test_arrhenius_and_vant_hoff(orc):
     c1 = orc.tconst(318.15)
     # 55 kJ/mol roughly doubles the rates per 10 K near 35 C
     assert 1.8 < c1["arr"] < 2.1
+
+
+def test_vant_hoff_against_physical_tables(orc):
+    """Temperature dependence away from T_base, against measured values of
+    the constants at 35 C (308.15 K) from standard tables.  A flipped sign of
+    (1/T_base - 1/T), or a wrong enthalpy scale, moves every one of them far
+    outside these bands (e.g. pK_w 14.32 instead of 13.68).
+
+    Table values (independent of the parameter file):
+      * pK_w(35 C) = 13.680 (ion product of water, CRC Handbook);
+      * p_h2o(35 C) = 5.628 kPa (saturated water vapour, CRC Handbook); the
+        parameter set's exponential form is an approximation, within 2 %;
+      * pK_a1 of carbonic acid 6.309 at 35 C (Harned & Davis 1943);
+      * pK_a of NH4+ 0.09018 + 2729.92/T (Emerson et al. 1975): 8.949;
+      * Henry's law solubility ratios k_H(35 C)/k_H(25 C) from the
+        d ln k_H / d(1/T) of Sander's compilation (2015): CO2 2400 K -> 0.770,
+        CH4 1600 K -> 0.840, H2 500 K -> 0.947.
+    """
+    c = orc.tconst(308.15)
+    cb = orc.tconst(298.15)
+    assert abs(-math.log10(c["K_w"]) - 13.680) < 0.01
+    assert abs(c["p_h2o"] / 0.05628 - 1.0) < 0.02
+    assert abs(-math.log10(c["K_a_co2"]) - 6.309) < 0.01
+    assert abs(-math.log10(c["K_a_IN"]) - (0.09018 + 2729.92 / 308.15)) < 0.02
+    assert abs(c["K_H_co2"] / cb["K_H_co2"] / 0.770 - 1.0) < 0.02
+    assert abs(c["K_H_ch4"] / cb["K_H_ch4"] / 0.840 - 1.0) < 0.02
+    assert abs(c["K_H_h2"] / cb["K_H_h2"] / 0.947 - 1.0) < 0.01
+    # R T in bar m3/kmol at 35 C (ideal gas): 0.0831446 * 308.15
+    assert abs(c["RT"] - 25.6211) < 1e-3
+
+
+def _headspace_state(T, p_h2, p_ch4, p_co2):
+    """Nominal liquid with the headspace set to given partial pressures
+    (bar); COD per kmol is 16 for H2 and 64 for CH4."""
+    x, _, _, _ = nominal()
+    x = x.copy()
+    RT = 0.083145 * T
+    x[IX["G_h2"]] = 16.0 * p_h2 / RT
+    x[IX["G_ch4"]] = 64.0 * p_ch4 / RT
+    x[IX["G_co2"]] = p_co2 / RT
+    return x
+
+
+def test_valve_law_worked_example(orc):
+    """Gas outflow through the headspace valve (sec. 2.2 gas release; Table 1
+    P_atm = 1.013 bar, tank V_liq = 3400 m3 with k_p = 5e4 m3/(d bar)).
+
+    Worked by hand at T_base = 298.15 K, where p_h2o is its base value
+    0.0313 bar: p_ch4 = 1.2, p_co2 = 0.7947, p_h2 = 0 bar give
+    P_gas = 1.2 + 0.7947 + 0.0313 = 2.026 bar = 2 P_atm.  The outflow,
+    k_p (P_gas - P_atm) P_gas / P_atm = 5e4 * 1.013 * 2 = 101,300 m3/d for
+    the tank, i.e. 101300/3400 = 29.7941176... per m3 of liquid; its methane
+    share is q p_ch4 / P_gas = 50,000 * 1.2 = 60,000 m3/d and its CO2 share
+    50,000 * 0.7947 = 39,735 m3/d.  Dropping the P_gas/P_atm factor gives
+    50,650; using P_gas instead of the overpressure gives 202,600."""
+    T = 298.15
+    x = _headspace_state(T, 0.0, 1.2, 0.7947)
+    q = orc.gas_flux(x, T, 3400.0)
+    assert abs(q[0] - 101300.0) < 1e-8 * 101300.0
+    assert q[1] == 0.0
+    assert abs(q[2] - 60000.0) < 1e-8 * 60000.0
+    assert abs(q[3] - 39735.0) < 1e-8 * 39735.0
+    r = orc.rates(x, T, 1e-7)
+    assert abs(r[22] - 101300.0 / 3400.0) < 1e-12 * 30.0
+    assert abs(r[26] - 2.026) < 1e-12
+    # the rates and the headspace balance use the same outflow: with the
+    # liquid-gas transfer switched off, dG_i/dt = -(q/V_liq) G_i / (V_gas/V_liq)
+    v = values()
+    v["k_L_a"] = 0.0
+    o2 = Oracle(v, rtol=1e-8)
+    f, _, _ = o2.rhs(x, T, 0.0, np.zeros(NLIQ))
+    dx = np.zeros(NX)
+    dx[DIFF] = f
+    vg = v["V_gas_per_V_liq"]
+    for g in ["G_ch4", "G_co2"]:
+        want = -(101300.0 / 3400.0) * x[IX[g]] / vg
+        assert abs(dx[IX[g]] - want) < 1e-12 * abs(want), g
+
+
+def test_valve_closed_at_or_below_atmosphere(orc):
+    """No flow while the headspace is at or below P_atm (the valve does not
+    draw air in): P_gas = 0.9 bar and P_gas = P_atm exactly both give zero,
+    and the methane share is zero with it."""
+    T = 298.15
+    for p_ch4, p_co2 in [(0.5, 0.3687), (0.6, 1.013 - 0.6 - 0.0313)]:
+        x = _headspace_state(T, 0.0, p_ch4, p_co2)
+        P = p_ch4 + p_co2 + 0.0313
+        assert P <= 1.013 + 1e-15
+        q = orc.gas_flux(x, T, 3400.0)
+        assert (q == 0.0).all(), (P, q)
+        assert orc.rates(x, T, 1e-7)[22] == 0.0
+    # just above P_atm the flow starts at zero and grows linearly:
+    # q ~ k_p dP for a small overpressure dP
+    dP = 1e-6
+    x = _headspace_state(T, 0.0, 0.6, 1.013 - 0.6 - 0.0313 + dP)
+    q = orc.gas_flux(x, T, 3400.0)[0]
+    assert abs(q / (5e4 * dP) - 1.0) < 1e-5
 
 
 # ---------------------------------------------------------------------------
