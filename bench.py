@@ -47,9 +47,11 @@ def step_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the step kernel from the committed counter
-    summary, or None when the kernel sources changed since it was taken."""
+def measured_traffic(K: int):
+    """Calibrated HBM bytes per launch of the step kernel, averaged over the
+    first K coupling intervals, from the committed counter summary (one value
+    per interval of the profiled run); None when the kernel sources changed
+    since the counters were taken or the profile covers fewer intervals."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
@@ -58,9 +60,12 @@ def measured_traffic():
     if kv.get("kernel_source_sha256") != step_source_hash():
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        per = [float(v) for v in kv["traffic_bytes_per_interval"].split(",")]
     except (KeyError, ValueError):
         return None
+    if K > len(per):
+        return None
+    return sum(per[:K]) / K
 
 
 def parse():
@@ -118,9 +123,11 @@ def parse():
                     help="work-queue order of the step kernel (cost: expected step count "
                          "from the previous interval, largest first)")
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--cpu-sample", type=int, default=16384,
-                    help="particles of the oracle CPU-baseline sample (0: skip)")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="particles of the oracle CPU-baseline sample (0: skip; default "
+                         "163,840 particle-steps over the timed horizon)")
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="coupling steps of the CPU sample (default: the timed steps)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the timed region, one device-to-device copy of this size "
                          "(the known-size kernel that calibrates HBM byte counters)")
@@ -256,9 +263,11 @@ def main():
     achieved = flop / kern_s
     value = w.n * K / (total_ms / 1e3)
     traffic = None
-    if (args.n == 1 << 20 and K == 10 and args.rtol == 1e-8 and args.variant in (-1, 2) and
-            args.rate_precision == 0):
-        traffic = measured_traffic()
+    if (args.n == 1 << 20 and args.warmup >= 0 and args.rtol == 1e-8 and
+            args.variant in (-1, 2) and args.rate_precision == 0 and args.order == "cost" and
+            args.blocks_per_cu == 0):
+        traffic = measured_traffic(K)
+    size = "2^20" if w.n == 1 << 20 else str(w.n)
     out = {
         "metric": "ADM1 particle-steps/sec (FP64 integrator vs gated surrogate) at stated error",
         "value": value,
@@ -272,9 +281,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.rate_precision == 0 else "f64 (rates f32)",
         "data": "synthetic",
-        "config": {"workload": "batched ADM1 population: 2^20 particles, T U(30,40) C, 5% "
-                               "pulsed feed zone, 10 coupling steps of 1/96 d, rtol 1e-8"
-                   if args.n == 1 << 20 else f"batched ADM1 population, n={args.n}",
+        "config": {"workload": f"batched ADM1 population: {size} particles, T U(30,40) C, "
+                               f"5% pulsed feed zone, {K} coupling steps of 1/96 d from a "
+                               f"cold start, rtol {args.rtol:g}",
                    "particles": w.n, "coupling_steps": K, "dt_days": w.dt, "rtol": args.rtol,
                    "path": "fp64 integrator" if args.rate_precision == 0 else
                    "fp64 integrator, fp32 rates", "variant": args.variant,
@@ -290,32 +299,44 @@ def main():
                    "hbm_bytes_per_particle_step": F.BYTES_PER_PARTICLE_STEP,
                    "hbm_frac": w.n * F.BYTES_PER_PARTICLE_STEP / (sum(step_ms) / K / 1e3)
                    / PEAK_HBM,
-                   "step_ms": step_ms, "wall_s": wall},
+                   "step_ms": step_ms, "wall_s": wall,
+                   "cold_interval_ms": step_ms[0],
+                   "warm_interval_mean_ms": (sum(step_ms[1:]) / (K - 1)) if K > 1 else None},
     }
-    if args.cpu_sample > 0:
-        out["cpu_baseline"] = cpu_baseline(w, args.rtol, args.cpu_sample, args.cpu_steps)
+    cpu_steps = args.cpu_steps or K
+    n_sample = args.cpu_sample
+    if n_sample is None:
+        n_sample = int(min(16384, max(1024, round(163840 / cpu_steps))))
+    if n_sample > 0:
+        out["cpu_baseline"] = cpu_baseline(w, args.rtol, n_sample, cpu_steps)
         out["detail"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+        out["detail"]["gpu_over_cpu_horizon"] = (f"both over coupling steps 0..{K - 1}"
+                                                 if cpu_steps == K else
+                                                 f"GPU {K} steps, CPU {cpu_steps} steps")
     print(json.dumps(out))
 
 
 def fixed_cpu_baseline(w, dt, substeps, method, n_sample, steps):
-    """The oracle's fixed-step integrator, as it stands (one particle per
-    call, one thread), on a seeded sample of the same population."""
+    """The oracle's fixed-step integrator, as it stands, on a seeded sample of
+    the same population: equal particle chunks over all host cores (the
+    paper's CPU parallelisation, sec. 4.3), through the oracle's own threaded
+    C loop."""
     from oracle.adm1 import Oracle
     from paper_2311_08927_amd import workloads as W
     orc = Oracle(W.params_path(), rtol=1e-8, atol=W.atol_vector(1e-8))
     idx = np.sort(np.random.default_rng(123).choice(w.n, min(n_sample, w.n), replace=False))
-    X = w.X[:, idx].copy()
+    sub = W.subset(w, idx)
+    cores = len(os.sched_getaffinity(0))
+    X = sub.X.copy()
     t0 = time.perf_counter()
     for _ in range(steps):
-        for j, i in enumerate(idx):
-            X[:, j] = orc.fixed(X[:, j], w.T[i], w.D[i], w.feed[w.fidx[i]], dt, substeps,
-                                method)
+        orc.run_fixed(X, sub.T, sub.D, sub.fidx, sub.feed, dt, substeps, method, n=sub.n,
+                      nthreads=cores)
     el = time.perf_counter() - t0
-    return {"value": len(idx) * steps / el, "unit": "particle-steps/s", "cores": 1,
+    return {"value": sub.n * steps / el, "unit": "particle-steps/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{len(idx)} particles x {steps} coupling intervals of the same "
-                      f"population, one particle per call on one thread, {el:.1f} s"}
+            "sample": f"{sub.n} particles x {steps} coupling intervals of the same "
+                      f"population, equal particle chunks over {cores} threads, {el:.1f} s"}
 
 
 def fixed_main(args):
@@ -400,9 +421,10 @@ def fixed_main(args):
                    "hbm_bytes_per_particle_step": F.BYTES_FIXED,
                    "hbm_frac": w.n * F.BYTES_FIXED / (sum(launch_ms) / K / 1e3) / PEAK_HBM},
     }
-    if args.cpu_sample > 0:
+    n_sample = 65536 if args.cpu_sample is None else args.cpu_sample
+    if n_sample > 0:
         out["cpu_baseline"] = fixed_cpu_baseline(w, dt, args.substeps, args.method,
-                                                 args.cpu_sample, args.cpu_steps)
+                                                 n_sample, args.cpu_steps or 10)
         out["detail"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
     print(json.dumps(out))
 

@@ -293,6 +293,32 @@ int adm1_rhs(adm1_ctx *ctx, const double *state, int64_t ld, const double *temp_
              const adm1_feed *feed, int64_t n, double *dxdt, int64_t ld_out, double *H_out,
              int32_t rate_precision, uint8_t *status, void *stream);
 
+/* Eq. 7 alone (sec. 2.2: the charge balance fixes S_H+ once the ion totals
+ * are known; the ions S_va-, S_bu-, S_pro-, S_ac-, S_hco3- and S_nh3 are
+ * the equilibrium fractions K_a/(K_a + S_H+) of their totals at the
+ * particle's temperature).  Solves for S_H+ of particles 0..n-1 from the
+ * totals in state (entries 3-6, 9, 10, 24, 25 are read) by the Newton
+ * iteration of the step, to a relative change below sqrt(opts.newton_tol)/10.
+ * H_guess (nullable, [n]): starting values (<= 0 or NULL: 1e-7 kmol/m3).
+ * Outputs: H_out [n] S_H+ in kmol/m3; pH_out (nullable) [n] = -log10(S_H+);
+ * status (nullable) [n]: 0 ok, 1 no convergence, 4 non-finite input or
+ * T <= 0; the outputs of a failed particle are NaN.  Asynchronous on
+ * `stream`; no allocation. */
+int adm1_solve_ph(adm1_ctx *ctx, const double *state, int64_t ld, const double *temp_K,
+                  int64_t n, const double *H_guess, double *H_out, double *pH_out,
+                  uint8_t *status, void *stream);
+
+/* Outcome counts of the last adm1_step_particles, adm1_step_fixed or
+ * adm1_surrogate_step call on this context (also when replayed from a
+ * captured graph), counted on the device from its status array after the
+ * step: host_out[0] particles with a nonzero status code, host_out[1..4]
+ * particles with code 1..4, host_out[5] particles with code 0 whose
+ * negative-entry bit is set, host_out[6] particles counted (the call's n).
+ * host_out is HOST memory of 7 int64.  Synchronous: waits for `stream`
+ * (where the step was enqueued) and reads the counters. */
+enum { ADM1_FAIL_SLOTS = 7 };
+int adm1_last_failures(adm1_ctx *ctx, int64_t *host_out, void *stream);
+
 /* Total Jacobian df/dy of the 28 differential entries (the algebraic
  * unknowns eliminated through eqs. 7-8): float64 [n][28][28] row-major, for
  * tests.  Status (nullable) as in adm1_rhs. */

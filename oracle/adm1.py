@@ -58,6 +58,11 @@ def lib():
                               ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int64,
                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                               ctypes.c_void_p, ctypes.c_int]
+        L.orc_run_fixed.restype = ctypes.c_int
+        L.orc_run_fixed.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_int64, dp,
+                                    dp, ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_int]
         L.orc_rhs.restype = ctypes.c_int
         L.orc_rhs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_double,
                               ctypes.c_double, dp, dp, dp, dp]
@@ -220,6 +225,29 @@ class Oracle:
         if rc != 0:
             raise RuntimeError("fixed-step integration failed")
         return x
+
+    def run_fixed(self, X, T, D, fidx, feed, dt, nsteps, method="euler", n=None,
+                  nthreads=None):
+        """The fixed-step scheme (see `fixed`) over particles 0..n-1 of X[35][ld]
+        in place, equal particle chunks over nthreads threads.  Returns status
+        uint8[n] (1 where a particle's integration failed)."""
+        assert X.dtype == np.float64 and X.flags["C_CONTIGUOUS"] and X.shape[0] == NX
+        ld = X.shape[1]
+        n = ld if n is None else n
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        fidx = np.ascontiguousarray(fidx, dtype=np.int32)
+        feed = np.ascontiguousarray(feed, dtype=np.float64)
+        code = {"rk4": 0, "rodas4": 1, "euler": 2}[method]
+        status = np.zeros(n, dtype=np.uint8)
+        if nthreads is None:
+            nthreads = len(os.sched_getaffinity(0))
+        rc = lib().orc_run_fixed(ctypes.byref(self._p), ctypes.byref(self._o), _dp(X), ld,
+                                 _dp(T), _dp(D), _vp(fidx), _dp(feed), dt, int(nsteps), code,
+                                 n, _vp(status), int(nthreads))
+        if rc != 0:
+            raise RuntimeError("oracle fixed-step run failed")
+        return status
 
     # -- batched step ----------------------------------------------------------
     def step(self, X, T, D, fidx, feed, dt, H=None, hlast=None, nthreads=None,

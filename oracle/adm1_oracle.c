@@ -1070,3 +1070,52 @@ int orc_fixed(const orc_params *p, const orc_opts *o, double *x, double T, doubl
     for (int i = 0; i < NX; i++) x[i] = creal(xc[i]);
     return 0;
 }
+
+/* The fixed-step scheme over particles 0..n-1 of x[35][ld], in equal chunks
+ * over nthreads threads (the paper's CPU parallelisation, sec. 4.3): each
+ * particle advances by dt in nsteps steps of `method` (orc_fixed).  status[i]
+ * is 0, or 1 where the integration failed (the particle keeps its input). */
+typedef struct {
+    const orc_params *p; const orc_opts *o;
+    double *X; int64_t ld; const double *T; const double *D; const int32_t *fidx;
+    const double *feed; double dt; int nsteps, method; uint8_t *status; int64_t i0, i1;
+} orc_fixed_job;
+
+static void *run_fixed_chunk(void *arg)
+{
+    orc_fixed_job *j = (orc_fixed_job *)arg;
+    for (int64_t i = j->i0; i < j->i1; i++) {
+        double x[NX];
+        gather(j->X, j->ld, i, x);
+        const int rc = orc_fixed(j->p, j->o, x, j->T[i], j->D[i],
+                                 j->feed + (int64_t)j->fidx[i] * NLIQ, j->dt, j->nsteps,
+                                 j->method);
+        if (rc == 0) scatter(j->X, j->ld, i, x);
+        j->status[i] = rc == 0 ? 0 : 1;
+    }
+    return NULL;
+}
+
+int orc_run_fixed(const orc_params *p, const orc_opts *o, double *X, int64_t ld,
+                  const double *T, const double *D, const int32_t *fidx, const double *feed,
+                  double dt, int nsteps, int method, int64_t n, uint8_t *status, int nthreads)
+{
+    if (orc_check_params(p) || nsteps < 1) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > n) nthreads = (int)(n > 0 ? n : 1);
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    orc_fixed_job jobs[256];
+    for (int t = 0; t < nthreads; t++) {
+        orc_fixed_job *j = &jobs[t];
+        j->p = p; j->o = o; j->X = X; j->ld = ld; j->T = T; j->D = D; j->fidx = fidx;
+        j->feed = feed; j->dt = dt; j->nsteps = nsteps; j->method = method;
+        j->status = status;
+        j->i0 = n * t / nthreads;
+        j->i1 = n * (t + 1) / nthreads;
+    }
+    for (int t = 1; t < nthreads; t++) pthread_create(&th[t], NULL, run_fixed_chunk, &jobs[t]);
+    run_fixed_chunk(&jobs[0]);
+    for (int t = 1; t < nthreads; t++) pthread_join(th[t], NULL);
+    return 0;
+}

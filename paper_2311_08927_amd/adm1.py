@@ -74,6 +74,10 @@ def lib():
         L.adm1_gas_flux.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, vp, vp]
         L.adm1_rhs.restype = ctypes.c_int
         L.adm1_rhs.argtypes = [vp, vp, i64, vp, vp, i64, vp, i64, vp, i32, vp, vp]
+        L.adm1_solve_ph.restype = ctypes.c_int
+        L.adm1_solve_ph.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.adm1_last_failures.restype = ctypes.c_int
+        L.adm1_last_failures.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp]
         L.adm1_jacobian.restype = ctypes.c_int
         L.adm1_jacobian.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, vp]
         L.adm1_set_launch.restype = ctypes.c_int
@@ -217,6 +221,27 @@ def adm1_rhs(ctx, state, ld, temp_K, feed: adm1_feed, n, dxdt, ld_out, H_out=Non
     if check:
         _check(rc, "adm1_rhs")
     return rc
+
+
+def adm1_solve_ph(ctx, state, ld, temp_K, n, H_guess, H_out, pH_out=None, status=None,
+                  stream=None, check=True) -> int:
+    rc = lib().adm1_solve_ph(ctx, _ptr(state), int(ld), _ptr(temp_K), int(n), _ptr(H_guess),
+                             _ptr(H_out), _ptr(pH_out), _ptr(status), _stream(stream))
+    if check:
+        _check(rc, "adm1_solve_ph")
+    return rc
+
+
+FAIL_SLOTS = 7
+FAIL_NAMES = ["failed", "algebraic", "underflow", "max_steps", "nonfinite", "negative",
+              "counted"]
+
+
+def adm1_last_failures(ctx, stream=None) -> dict:
+    """Outcome counts of the last step call (synchronous)."""
+    out = (ctypes.c_int64 * FAIL_SLOTS)()
+    _check(lib().adm1_last_failures(ctx, out, _stream(stream)), "adm1_last_failures")
+    return dict(zip(FAIL_NAMES, [int(v) for v in out]))
 
 
 def adm1_jacobian(ctx, state, ld, temp_K, feed: adm1_feed, n, J, status=None, stream=None,
@@ -418,6 +443,19 @@ class Context:
         adm1_rhs(self.handle, state, ld, T, feed_struct(D, fidx, S_in), n, dxdt, ld, H,
                  rate_precision, st, stream)
         return dxdt, H, st
+
+    def solve_ph(self, state, T, n=None, H_guess=None, stream=None):
+        """Eq. 7 alone: (S_H+, pH, status) of each particle's totals."""
+        import torch
+        n = state.shape[1] if n is None else n
+        H = torch.empty(n, dtype=torch.float64, device=state.device)
+        pH = torch.empty(n, dtype=torch.float64, device=state.device)
+        st = torch.empty(n, dtype=torch.uint8, device=state.device)
+        adm1_solve_ph(self.handle, state, state.shape[1], T, n, H_guess, H, pH, st, stream)
+        return H, pH, st
+
+    def last_failures(self, stream=None) -> dict:
+        return adm1_last_failures(self.handle, stream)
 
     def jacobian(self, state, T, D, fidx, S_in, n=None, stream=None):
         import torch

@@ -44,6 +44,7 @@ const char kParamNames[] =
 
 // every field of adm1_params is listed once, in order
 #define ADM1_COUNT(n) +1
+static_assert(ADM1_FAIL_SLOTS == adm1::kFailSlots, "outcome counter slots");
 static_assert(sizeof(adm1_params) == sizeof(double) * (0 ADM1_PARAM_FIELDS(ADM1_COUNT)),
               "adm1_params field list out of sync");
 #undef ADM1_COUNT
@@ -306,13 +307,17 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
         hipMalloc(&c->d_order, (size_t)(n_max > 0 ? n_max : 1) * sizeof(int32_t)) !=
             hipSuccess ||
         hipMalloc(&c->d_order_work, order_work) != hipSuccess ||
-        hipMemset(c->d_order_work, 0, order_work) != hipSuccess) {
+        hipMemset(c->d_order_work, 0, order_work) != hipSuccess ||
+        hipMalloc(&c->d_fail, adm1::kFailSlots * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->d_fail, 0, adm1::kFailSlots * sizeof(unsigned long long)) !=
+            hipSuccess) {
         (void)hipGetLastError();
         if (c->d_queue) (void)hipFree(c->d_queue);
         if (c->d_partial) (void)hipFree(c->d_partial);
         if (c->d_params) (void)hipFree(c->d_params);
         if (c->d_order) (void)hipFree(c->d_order);
         if (c->d_order_work) (void)hipFree(c->d_order_work);
+        if (c->d_fail) (void)hipFree(c->d_fail);
         delete c;
         return ADM1_E_NOMEM;
     }
@@ -341,6 +346,7 @@ void adm1_destroy(adm1_ctx* ctx)
     (void)hipFree(ctx->d_params);
     (void)hipFree(ctx->d_order);
     (void)hipFree(ctx->d_order_work);
+    (void)hipFree(ctx->d_fail);
     delete ctx;
 }
 
@@ -360,7 +366,8 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
         if ((aux->H && !is_device(aux->H)) || (aux->h_last && !is_device(aux->h_last)))
             return ADM1_E_NOT_DEVICE;
     }
-    if (n == 0) return ADM1_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return hip_rc(adm1::launch_count_status(status, 0, ctx->d_fail, s));
     adm1::StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.p = ctx->dp;
@@ -372,12 +379,13 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
     a.pdev = ctx->d_params;
     int variant = ctx->opts.variant;
     if (variant < 0) variant = ctx->tuned_variant >= 0 ? ctx->tuned_variant : ADM1_VARIANT_SPARSE2;
-    hipStream_t s = (hipStream_t)stream;
     switch (variant) {
     case ADM1_VARIANT_DENSE1:
-        return hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, false, s));
+        rc = hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, false, s));
+        break;
     case ADM1_VARIANT_SPARSE1:
-        return hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, true, s));
+        rc = hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, true, s));
+        break;
     case ADM1_VARIANT_SPARSE2:
         // expensive particles first (predicted by the previous interval's
         // last step size) so that the queue's tail is made of cheap ones
@@ -389,11 +397,14 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
             a.index_count = ctx->d_order_work + 2 * adm1::kOrderBuckets;
             a.index_bound = n;
         }
-        return hip_rc(adm1::launch_step_sparse2(a, ctx->opts.rate_precision,
-                                                ctx->tuned_blocks_per_cu, s));
+        rc = hip_rc(adm1::launch_step_sparse2(a, ctx->opts.rate_precision,
+                                              ctx->tuned_blocks_per_cu, s));
+        break;
     default:
         return ADM1_E_VARIANT;
     }
+    if (rc) return rc;
+    return hip_rc(adm1::launch_count_status(status, n, ctx->d_fail, s));
 }
 
 int adm1_step_fixed(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,
@@ -410,14 +421,46 @@ int adm1_step_fixed(adm1_ctx* ctx, double* state, int64_t ld, const double* temp
     if (rc) return rc;
     if (!is_device(state) || !is_device(temp_K) || !is_device(status)) return ADM1_E_NOT_DEVICE;
     if ((H && !is_device(H)) || (newton && !is_device(newton))) return ADM1_E_NOT_DEVICE;
-    if (n == 0) return ADM1_OK;
+    if (n == 0) return hip_rc(adm1::launch_count_status(status, 0, ctx->d_fail, (hipStream_t)stream));
     adm1::FixedArgs a;
     std::memset(&a, 0, sizeof(a));
     a.p = ctx->dp;
     a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.D = feed->D; a.fidx = feed->idx;
     a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.dt = dt_days; a.substeps = substeps;
     a.method = method; a.H = H; a.status = status; a.newton = newton;
-    return hip_rc(adm1::launch_fixed(a, ctx->opts.rate_precision, (hipStream_t)stream));
+    rc = hip_rc(adm1::launch_fixed(a, ctx->opts.rate_precision, (hipStream_t)stream));
+    if (rc) return rc;
+    return hip_rc(adm1::launch_count_status(status, n, ctx->d_fail, (hipStream_t)stream));
+}
+
+int adm1_last_failures(adm1_ctx* ctx, int64_t* host_out, void* stream)
+{
+    if (!ctx || !host_out) return ADM1_E_NULL;
+    unsigned long long c[adm1::kFailSlots];
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(c, ctx->d_fail, sizeof(c), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_rc(e);
+    for (int k = 0; k < adm1::kFailSlots; ++k) host_out[k] = (int64_t)c[k];
+    return ADM1_OK;
+}
+
+int adm1_solve_ph(adm1_ctx* ctx, const double* state, int64_t ld, const double* temp_K,
+                  int64_t n, const double* H_guess, double* H_out, double* pH_out,
+                  uint8_t* status, void* stream)
+{
+    if (!ctx || !state || !temp_K || !H_out) return ADM1_E_NULL;
+    const int rc = check_layout(ctx, ld, n);
+    if (rc) return rc;
+    if (!is_device(state) || !is_device(temp_K) || !is_device(H_out)) return ADM1_E_NOT_DEVICE;
+    if ((H_guess && !is_device(H_guess)) || (pH_out && !is_device(pH_out)) ||
+        (status && !is_device(status)))
+        return ADM1_E_NOT_DEVICE;
+    adm1::PhArgs a;
+    a.p = ctx->dp;
+    a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.guess = H_guess;
+    a.H_out = H_out; a.pH_out = pH_out; a.status = status;
+    return hip_rc(adm1::launch_solve_ph(a, (hipStream_t)stream));
 }
 
 int adm1_set_order(adm1_ctx* ctx, int32_t mode)

@@ -21,6 +21,7 @@ struct adm1_ctx {
     int order_mode;      // ADM1_ORDER_* of the step kernel's work queue
     int32_t* d_order;    // cost-ordered particle list [max(n_max, 1)]
     int32_t* d_order_work;  // its histogram, bucket cursors and length
+    unsigned long long* d_fail;  // outcome counters of the last step call [kFailSlots]
 };
 
 // A captured coupling step (adm1_graph_capture_step and its surrogate

@@ -69,7 +69,26 @@ constexpr double kOrderRes = 8.0;
 hipError_t launch_cost_order(const double* hlast, const int32_t* list,
                              const int32_t* list_count, int64_t n, double dt, int32_t* work,
                              int32_t* order, hipStream_t s);
+struct PhArgs {
+    DevParams p;
+    const double* state;    // [35][ld]
+    int64_t ld, n;
+    const double* T;        // [n]
+    const double* guess;    // [n] nullable
+    double* H_out;          // [n]
+    double* pH_out;         // [n] nullable
+    uint8_t* status;        // [n] nullable
+};
+
+// Outcome counters of the last step call on a context (adm1_last_failures):
+// [0] particles with a nonzero status code, [1..4] codes 1..4, [5] code 0
+// with the negative-entry bit, [6] particles counted.
+constexpr int kFailSlots = 7;
+
 hipError_t launch_rhs(const RhsArgs& a, int rate_precision, hipStream_t s);
+hipError_t launch_solve_ph(const PhArgs& a, hipStream_t s);
+hipError_t launch_count_status(const uint8_t* status, int64_t n, unsigned long long* counts,
+                               hipStream_t s);
 hipError_t launch_jacobian(const RhsArgs& a, double* J, hipStream_t s);
 hipError_t launch_gasflux(const GasArgs& a, int nblocks, double* totals, hipStream_t s);
 

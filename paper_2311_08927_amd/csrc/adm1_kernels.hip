@@ -420,6 +420,68 @@ __global__ void __launch_bounds__(64) k_rhs(RhsArgs a)
     if (a.status) a.status[i] = rc ? 1 : 0;
 }
 
+// Eq. 7 alone: S_H+ of each particle's totals (the ions as equilibrium
+// fractions), by the same Newton iteration the right-hand side uses.
+__global__ void __launch_bounds__(64) k_solve_ph(PhArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const DevParams& p = a.p;
+    double y[NY];
+    bool fin = true;
+    for (int k = 0; k < NY; ++k) {
+        y[k] = a.state[state_row(k) * a.ld + i];
+        fin = fin && isfinite(y[k]);
+    }
+    const double T = a.T[i];
+    fin = fin && isfinite(T) && T > 0.0;
+    double H = a.guess ? a.guess[i] : -1.0;
+    int it = 0;
+    int st = 4;
+    if (fin) {
+        const TConst c = tconst(p, T);
+        st = solve_H(p, c, y, H, it) ? 1 : 0;
+    }
+    a.H_out[i] = st ? NAN : H;
+    if (a.pH_out) a.pH_out[i] = st ? NAN : -log10(H);
+    if (a.status) a.status[i] = (uint8_t)st;
+}
+
+// Outcome counters: one pass over the status bytes, block sums in LDS, one
+// atomic per slot and block.
+__global__ void k_count_reset(unsigned long long* c)
+{
+    if (threadIdx.x < kFailSlots) c[threadIdx.x] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_count_status(const uint8_t* status, int64_t n,
+                                                      unsigned long long* c)
+{
+    __shared__ unsigned int part[kFailSlots][256];
+    unsigned int loc[kFailSlots] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned v = status[i];
+        const unsigned code = v & 0x7Fu;
+        loc[0] += code != 0;
+        loc[1] += code == 1;
+        loc[2] += code == 2;
+        loc[3] += code == 3;
+        loc[4] += code == 4;
+        loc[5] += code == 0 && (v & 0x80u);
+        loc[6] += 1;
+    }
+    for (int k = 0; k < kFailSlots; ++k) part[k][threadIdx.x] = loc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < kFailSlots; ++k) part[k][threadIdx.x] += part[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < kFailSlots && part[threadIdx.x][0])
+        atomicAdd(&c[threadIdx.x], (unsigned long long)part[threadIdx.x][0]);
+}
+
 // Total Jacobian: minus the Schur complement of the constraint block of the
 // bordered matrix taken at alpha = 0.
 __global__ void __launch_bounds__(64) k_jacobian(RhsArgs a, double* J)
@@ -563,6 +625,26 @@ hipError_t launch_rhs(const RhsArgs& a, int rate_precision, hipStream_t s)
         hipLaunchKernelGGL(k_rhs<float>, dim3(grid), dim3(64), 0, s, a);
     else
         hipLaunchKernelGGL(k_rhs<double>, dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_ph(const PhArgs& a, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((a.n + 63) / 64);
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_solve_ph, dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_status(const uint8_t* status, int64_t n, unsigned long long* counts,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_reset, dim3(1), dim3(64), 0, s, counts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n <= 0) return e;
+    int64_t grid = (n + 256 * 16 - 1) / (256 * 16);
+    if (grid > 1024) grid = 1024;
+    hipLaunchKernelGGL(k_count_status, dim3((unsigned)grid), dim3(256), 0, s, status, n, counts);
     return hipGetLastError();
 }
 

@@ -609,7 +609,7 @@ int adm1_surrogate_step(adm1_surrogate* s, double* state, int64_t ld, const doub
     if ((rc = adm1_surrogate_gate(s, state, ld, temp_K, feed, dt_days, n, s->Y, gate, aux,
                                   status, nsteps, route, s->fb_idx, cnt, stream)))
         return rc;
-    if (n == 0) return ADM1_OK;
+    if (n == 0) return hip_rc(adm1::launch_count_status(status, 0, s->ctx->d_fail, st));
     adm1_ctx* ctx = s->ctx;
     adm1::StepArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -630,8 +630,10 @@ int adm1_surrogate_step(adm1_surrogate* s, double* state, int64_t ld, const doub
         a.index = ctx->d_order;
         a.index_count = ctx->d_order_work + 2 * adm1::kOrderBuckets;
     }
-    return hip_rc(adm1::launch_step_sparse2(a, ctx->opts.rate_precision, ctx->tuned_blocks_per_cu,
-                                            st));
+    rc = hip_rc(adm1::launch_step_sparse2(a, ctx->opts.rate_precision, ctx->tuned_blocks_per_cu,
+                                          st));
+    if (rc) return rc;
+    return hip_rc(adm1::launch_count_status(status, n, ctx->d_fail, st));
 }
 
 int adm1_surrogate_graph_capture_step(adm1_surrogate* s, double* state, int64_t ld,

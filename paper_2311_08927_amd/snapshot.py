@@ -37,24 +37,50 @@ def _lib():
     return L
 
 
-def _host_ptr(a):
-    """Address of a host array (numpy, or a CPU torch tensor), or None."""
+# rows and element type of each field (the file layout of adm1_snapshot_*)
+_FIELDS = {"pos": (3, np.float32), "vel": (3, np.float32), "rho": (1, np.float32),
+           "state": (35, np.float64)}
+
+
+def _host_ptr(a, name, ld, writable=False):
+    """Address of a host buffer for field `name` with row stride ld, or None.
+
+    The C routines move rows * ld elements at offsets r * ld and know nothing
+    of the buffer, so the buffer is checked here: host memory (numpy, or a
+    CPU torch tensor), C-contiguous, of the field's element type, shaped
+    [rows][ld] (or flat with at least rows * ld elements), and writable when
+    it is read into."""
     if a is None:
         return None
+    rows, dt = _FIELDS[name]
     if isinstance(a, np.ndarray):
-        if not a.flags["C_CONTIGUOUS"]:
-            raise ValueError("snapshot buffers must be C-contiguous")
-        return a.ctypes.data
-    if a.is_cuda:
-        raise ValueError("snapshot buffers are host memory")
-    return a.data_ptr()
+        contiguous, dtype, shape = a.flags["C_CONTIGUOUS"], a.dtype, a.shape
+        if writable and not a.flags["WRITEABLE"]:
+            raise ValueError(f"snapshot field {name}: buffer is read-only")
+        ptr = a.ctypes.data
+    else:
+        if a.is_cuda:
+            raise ValueError(f"snapshot field {name}: buffers are host memory")
+        contiguous, shape = a.is_contiguous(), tuple(a.shape)
+        dtype = np.dtype(str(a.dtype).replace("torch.", ""))
+        ptr = a.data_ptr()
+    if not contiguous:
+        raise ValueError(f"snapshot field {name}: buffer must be C-contiguous")
+    if dtype != np.dtype(dt):
+        raise ValueError(f"snapshot field {name}: dtype {dtype}, expected {np.dtype(dt)}")
+    size = int(np.prod(shape)) if len(shape) else 1
+    if len(shape) == 2 and (shape[1] != ld or shape[0] < rows):
+        raise ValueError(f"snapshot field {name}: shape {shape}, expected ({rows}, {ld})")
+    if len(shape) > 2 or size < rows * ld:
+        raise ValueError(f"snapshot field {name}: {size} elements, need {rows} x {ld}")
+    return ptr
 
 
 def adm1_snapshot_write(path, n, ld, time_s=0.0, pos=None, vel=None, rho=None, state=None,
                         check=True) -> int:
     rc = _lib().adm1_snapshot_write(os.fsencode(path), int(n), int(ld), float(time_s),
-                                    _host_ptr(pos), _host_ptr(vel), _host_ptr(rho),
-                                    _host_ptr(state))
+                                    _host_ptr(pos, "pos", ld), _host_ptr(vel, "vel", ld),
+                                    _host_ptr(rho, "rho", ld), _host_ptr(state, "state", ld))
     if check:
         A._check(rc, "adm1_snapshot_write")
     return rc
@@ -70,8 +96,10 @@ def adm1_snapshot_info(path):
 
 def adm1_snapshot_read(path, ld, pos=None, vel=None, rho=None, state=None, check=True):
     n = _i64()
-    rc = _lib().adm1_snapshot_read(os.fsencode(path), int(ld), _host_ptr(pos), _host_ptr(vel),
-                                   _host_ptr(rho), _host_ptr(state), ctypes.byref(n))
+    rc = _lib().adm1_snapshot_read(os.fsencode(path), int(ld),
+                                   _host_ptr(pos, "pos", ld, True), _host_ptr(vel, "vel", ld, True),
+                                   _host_ptr(rho, "rho", ld, True),
+                                   _host_ptr(state, "state", ld, True), ctypes.byref(n))
     if check:
         A._check(rc, "adm1_snapshot_read")
     return n.value if rc == 0 else rc

@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     fns = declared_functions()
     for f in ["adm1_init", "adm1_step_particles", "adm1_gas_flux", "adm1_rhs",
               "adm1_jacobian", "adm1_strerror", "adm1_destroy", "adm1_set_opts",
-              "adm1_param_names"]:
+              "adm1_param_names", "adm1_solve_ph", "adm1_last_failures"]:
         assert f in fns
 
 

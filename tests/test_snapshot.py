@@ -109,3 +109,36 @@ def test_errors(tmp_path):
     assert S.adm1_snapshot_write(p, 0, 1, 0.0) == 0   # empty snapshot
     assert S.adm1_snapshot_info(p) == (0, 0, 0.0)
     os.remove(p)
+
+
+def test_binding_rejects_buffers_that_do_not_fit(tmp_path):
+    """The C routines move rows x ld elements at offsets r x ld without
+    knowing the buffers' sizes: the binding refuses a buffer of the wrong
+    element type, shape, size or memory order before the call."""
+    import torch
+    p = str(tmp_path / "s.bin")
+    ld, n = 128, 100
+    pos = np.zeros((3, ld), np.float32)
+    state = np.zeros((35, ld), np.float64)
+    S.adm1_snapshot_write(p, n, ld, 0.0, pos, state=state)
+    bad = [
+        dict(state=np.zeros((35, ld), np.float32)),            # wrong dtype
+        dict(state=np.zeros((35, 2 * ld), np.float64)),        # row stride != ld
+        dict(state=np.zeros((34, ld), np.float64)),            # too few rows
+        dict(state=np.zeros((35 * ld - 1,), np.float64)),      # flat and too short
+        dict(pos=np.zeros((ld, 3), np.float32).T),             # not C-contiguous
+        dict(pos=torch.zeros((3, ld), dtype=torch.float64)),   # torch, wrong dtype
+        dict(rho=np.zeros(ld - 1, np.float32)),                # too short
+    ]
+    for kw in bad:
+        with pytest.raises(ValueError):
+            S.adm1_snapshot_read(p, ld, **kw)
+    ro = np.zeros((3, ld), np.float32)
+    ro.flags["WRITEABLE"] = False
+    with pytest.raises(ValueError):
+        S.adm1_snapshot_read(p, ld, pos=ro)
+    with pytest.raises(ValueError):
+        S.adm1_snapshot_write(p, n, ld, 0.0, state=np.zeros((35, 64), np.float64))
+    # fitting buffers, numpy and CPU torch, flat or [rows][ld], still pass
+    assert S.adm1_snapshot_read(p, ld, pos=torch.zeros((3, ld), dtype=torch.float32),
+                                state=np.zeros(35 * ld, np.float64)) == n
