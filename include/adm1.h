@@ -60,7 +60,8 @@ enum {
     ADM1_E_NOMEM = -7,       /* context scratch allocation failed (adm1_init) */
     ADM1_E_VARIANT = -8,     /* unknown kernel variant */
     ADM1_E_DT = -9,          /* dt not positive and finite */
-    ADM1_E_IO = -10          /* snapshot file missing, unreadable, unwritable or malformed */
+    ADM1_E_IO = -10,         /* snapshot file missing, unreadable, unwritable or malformed */
+    ADM1_E_STATIC = -11      /* n above ADM1_STATIC_MAX_N (adm1_step_particles_static) */
 };
 
 /* Status codes written per particle. */
@@ -175,6 +176,23 @@ int adm1_set_opts(adm1_ctx *ctx, const adm1_opts *o);
 int adm1_step_particles(adm1_ctx *ctx, double *state, int64_t ld, const double *temp_K,
                         const adm1_feed *feed, double dt_days, int64_t n, adm1_aux *aux,
                         uint8_t *status, int32_t *nsteps, void *stream);
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): adm1_step_particles
+ * with the kernels' work buffers (work-queue counter, cost-order histogram
+ * and the ordered particle list) in a static device array of the library
+ * instead of the context's scratch.  Same arguments, results and outcome
+ * counters (adm1_last_failures) as adm1_step_particles; the call allocates
+ * nothing.  Limit: n <= ADM1_STATIC_MAX_N particles, else ADM1_E_STATIC and
+ * nothing is enqueued.  Each device holds one copy of the array (about
+ * 4.2 MB) from the library's first use until the process ends; every call on
+ * a device shares it and the call clears what must start at zero, so calls
+ * that overlap on one device (concurrent streams, threads, contexts) race
+ * and must be serialised by the caller. */
+enum { ADM1_STATIC_MAX_N = 1048576 };
+int adm1_step_particles_static(adm1_ctx *ctx, double *state, int64_t ld, const double *temp_K,
+                               const adm1_feed *feed, double dt_days, int64_t n, adm1_aux *aux,
+                               uint8_t *status, int32_t *nsteps, void *stream);
 
 /* The paper's own fixed-step scheme (sec. 2.3: coupling steps small enough
  * that no step-size control is needed; sec. 4.3: Dt = 0.5 s in ten internal

@@ -22,7 +22,7 @@ NX, ND, NLIQ = 35, 28, 26
 VARIANT_DENSE1, VARIANT_SPARSE1, VARIANT_SPARSE2 = 0, 1, 2
 ERRORS = {0: "ok", -1: "E_NULL", -2: "E_SIZE", -3: "E_NOT_DEVICE", -4: "E_PARAMS",
           -5: "E_OPTS", -6: "E_FEED", -7: "E_NOMEM", -8: "E_VARIANT", -9: "E_DT",
-          -10: "E_IO"}
+          -10: "E_IO", -11: "E_STATIC"}
 
 _lib = None
 
@@ -68,6 +68,8 @@ def lib():
         L.adm1_destroy.argtypes = [vp]
         L.adm1_step_particles.restype = ctypes.c_int
         L.adm1_step_particles.argtypes = [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp]
+        L.adm1_step_particles_static.restype = ctypes.c_int
+        L.adm1_step_particles_static.argtypes = [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp]
         L.adm1_step_fixed.restype = ctypes.c_int
         L.adm1_step_fixed.argtypes = [vp, vp, i64, vp, vp, dbl, i32, i32, i64, vp, vp, vp, vp]
         L.adm1_gas_flux.restype = ctypes.c_int
@@ -188,6 +190,22 @@ def adm1_step_particles(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, n, aux
                                    _ptr(nsteps), _stream(stream))
     if check:
         _check(rc, "adm1_step_particles")
+    return rc
+
+
+STATIC_MAX_N = 1048576
+
+
+def adm1_step_particles_static(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, n, aux=None,
+                               status=None, nsteps=None, stream=None, check=True) -> int:
+    """adm1_step_particles with the work buffers in the library's static
+    device array (no allocation; n <= STATIC_MAX_N)."""
+    rc = lib().adm1_step_particles_static(ctx, _ptr(state), int(ld), _ptr(temp_K),
+                                          ctypes.byref(feed), float(dt_days), int(n),
+                                          None if aux is None else ctypes.byref(aux),
+                                          _ptr(status), _ptr(nsteps), _stream(stream))
+    if check:
+        _check(rc, "adm1_step_particles_static")
     return rc
 
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "adm1.h"
@@ -17,6 +18,48 @@ using adm1::DevParams;
 namespace {
 
 constexpr int kGasBlocks = 1024;
+
+// Scratch of adm1_step_particles_static, for callers that cannot allocate:
+// the work-queue counter (word 0 of a 64-word area), the cost-order
+// histogram, bucket cursors and list length, and the cost-ordered particle
+// list of at most ADM1_STATIC_MAX_N particles.  Each device holds its own
+// copy (4.2 MB) from module load to process end; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+constexpr int64_t kStaticQueueWords = 64;
+constexpr int64_t kStaticWorkWords = 2 * adm1::kOrderBuckets + 64;
+constexpr int64_t kStaticClearWords = kStaticQueueWords + kStaticWorkWords;
+constexpr int64_t kStaticWords = kStaticClearWords + ADM1_STATIC_MAX_N;
+static_assert(2 * adm1::kOrderBuckets + 1 <= kStaticWorkWords, "cost-order work area");
+static __device__ __align__(256) int32_t scratch[kStaticWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (looked up once).
+int static_scratch(int dev, int32_t** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return ADM1_E_NOMEM;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return e != hipSuccess ? (int)e : ADM1_E_NOMEM;
+        }
+        g_scratch_dev[dev] = (int32_t*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return ADM1_OK;
+}
+
+__global__ void k_clear_words(int32_t* p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
 
 #define ADM1_PARAM_FIELDS(X)                                                              \
     X(f_sI_xc) X(f_xI_xc) X(f_ch_xc) X(f_pr_xc) X(f_li_xc) X(N_xc) X(N_I) X(N_aa) X(N_bac) \
@@ -270,6 +313,7 @@ const char* adm1_strerror(int code)
     case ADM1_E_VARIANT: return "unknown step-kernel variant";
     case ADM1_E_DT: return "dt must be positive and finite";
     case ADM1_E_IO: return "snapshot file missing, unreadable, unwritable or malformed";
+    case ADM1_E_STATIC: return "n exceeds ADM1_STATIC_MAX_N, the capacity of the static scratch";
     default: break;
     }
     if (code > 0) return hipGetErrorString((hipError_t)code);
@@ -310,7 +354,8 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
         hipMemset(c->d_order_work, 0, order_work) != hipSuccess ||
         hipMalloc(&c->d_fail, adm1::kFailSlots * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(c->d_fail, 0, adm1::kFailSlots * sizeof(unsigned long long)) !=
-            hipSuccess) {
+            hipSuccess ||
+        static_scratch(c->device, &c->static_scratch) != ADM1_OK) {
         (void)hipGetLastError();
         if (c->d_queue) (void)hipFree(c->d_queue);
         if (c->d_partial) (void)hipFree(c->d_partial);
@@ -350,9 +395,19 @@ void adm1_destroy(adm1_ctx* ctx)
     delete ctx;
 }
 
-int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,
-                        const adm1_feed* feed, double dt_days, int64_t n, adm1_aux* aux,
-                        uint8_t* status, int32_t* nsteps, void* stream)
+namespace {
+
+// Work buffers of one step call: the queue counter, the cost-order work area
+// and the ordered particle list (context scratch, or the static array).
+struct StepScratch {
+    int32_t* queue;
+    int32_t* order_work;
+    int32_t* order;
+};
+
+int check_step(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,
+               const adm1_feed* feed, double dt_days, int64_t n, adm1_aux* aux,
+               uint8_t* status, int32_t* nsteps)
 {
     if (!ctx || !state || !temp_K || !status) return ADM1_E_NULL;
     int rc = check_layout(ctx, ld, n);
@@ -366,7 +421,15 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
         if ((aux->H && !is_device(aux->H)) || (aux->h_last && !is_device(aux->h_last)))
             return ADM1_E_NOT_DEVICE;
     }
-    hipStream_t s = (hipStream_t)stream;
+    return ADM1_OK;
+}
+
+// The step's launches on validated arguments: cost order (sparse2 with warm
+// starts), the step kernel, the outcome counters.
+int step_dispatch(adm1_ctx* ctx, const StepScratch& w, double* state, int64_t ld,
+                  const double* temp_K, const adm1_feed* feed, double dt_days, int64_t n,
+                  adm1_aux* aux, uint8_t* status, int32_t* nsteps, hipStream_t s)
+{
     if (n == 0) return hip_rc(adm1::launch_count_status(status, 0, ctx->d_fail, s));
     adm1::StepArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -375,10 +438,11 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
     a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.dt = dt_days;
     a.H = aux ? aux->H : nullptr;
     a.hlast = aux ? aux->h_last : nullptr;
-    a.status = status; a.nsteps = nsteps; a.queue = ctx->d_queue;
+    a.status = status; a.nsteps = nsteps; a.queue = w.queue;
     a.pdev = ctx->d_params;
     int variant = ctx->opts.variant;
     if (variant < 0) variant = ctx->tuned_variant >= 0 ? ctx->tuned_variant : ADM1_VARIANT_SPARSE2;
+    int rc = ADM1_OK;
     switch (variant) {
     case ADM1_VARIANT_DENSE1:
         rc = hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, false, s));
@@ -391,10 +455,10 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
         // last step size) so that the queue's tail is made of cheap ones
         if (ctx->order_mode == ADM1_ORDER_COST && a.hlast && n <= INT32_MAX) {
             rc = hip_rc(adm1::launch_cost_order(a.hlast, nullptr, nullptr, n, dt_days,
-                                                ctx->d_order_work, ctx->d_order, s));
+                                                w.order_work, w.order, s));
             if (rc) return rc;
-            a.index = ctx->d_order;
-            a.index_count = ctx->d_order_work + 2 * adm1::kOrderBuckets;
+            a.index = w.order;
+            a.index_count = w.order_work + 2 * adm1::kOrderBuckets;
             a.index_bound = n;
         }
         rc = hip_rc(adm1::launch_step_sparse2(a, ctx->opts.rate_precision,
@@ -405,6 +469,37 @@ int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* 
     }
     if (rc) return rc;
     return hip_rc(adm1::launch_count_status(status, n, ctx->d_fail, s));
+}
+
+}  // namespace
+
+int adm1_step_particles(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,
+                        const adm1_feed* feed, double dt_days, int64_t n, adm1_aux* aux,
+                        uint8_t* status, int32_t* nsteps, void* stream)
+{
+    const int rc = check_step(ctx, state, ld, temp_K, feed, dt_days, n, aux, status, nsteps);
+    if (rc) return rc;
+    const StepScratch w{ctx->d_queue, ctx->d_order_work, ctx->d_order};
+    return step_dispatch(ctx, w, state, ld, temp_K, feed, dt_days, n, aux, status, nsteps,
+                         (hipStream_t)stream);
+}
+
+int adm1_step_particles_static(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,
+                               const adm1_feed* feed, double dt_days, int64_t n, adm1_aux* aux,
+                               uint8_t* status, int32_t* nsteps, void* stream)
+{
+    int rc = check_step(ctx, state, ld, temp_K, feed, dt_days, n, aux, status, nsteps);
+    if (rc) return rc;
+    if (n > ADM1_STATIC_MAX_N) return ADM1_E_STATIC;
+    int32_t* base = ctx->static_scratch;
+    if (!base) return ADM1_E_NOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    // the array keeps the last call's contents: clear the counter and the
+    // cost-order histogram, which the kernels expect to start at zero
+    hipLaunchKernelGGL(k_clear_words, dim3(9), dim3(256), 0, s, base, kStaticClearWords);
+    if ((rc = hip_rc(hipGetLastError()))) return rc;
+    const StepScratch w{base, base + kStaticQueueWords, base + kStaticClearWords};
+    return step_dispatch(ctx, w, state, ld, temp_K, feed, dt_days, n, aux, status, nsteps, s);
 }
 
 int adm1_step_fixed(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,

@@ -22,6 +22,7 @@ struct adm1_ctx {
     int32_t* d_order;    // cost-ordered particle list [max(n_max, 1)]
     int32_t* d_order_work;  // its histogram, bucket cursors and length
     unsigned long long* d_fail;  // outcome counters of the last step call [kFailSlots]
+    int32_t* static_scratch;     // this device's address of the library's static scratch
 };
 
 // A captured coupling step (adm1_graph_capture_step and its surrogate
