@@ -152,6 +152,7 @@ int derive(const adm1_params& p, DevParams& d)
         if (!(ul[k] > ll[k])) return ADM1_E_PARAMS;
         d.pH_n[k] = 3.0 / (ul[k] - ll[k]);
         d.pH_K[k] = std::pow(10.0, -0.5 * (ll[k] + ul[k]));
+        d.pH_invK[k] = 1.0 / d.pH_K[k];
         const double r = std::nearbyint(d.pH_n[k]);
         d.pH_nint[k] = (std::fabs(d.pH_n[k] - r) < 1e-12 && r >= 1 && r <= 4) ? (int)r : 0;
     }
@@ -205,6 +206,8 @@ int derive(const adm1_params& p, DevParams& d)
     d.K_a_va = p.K_a_va; d.K_a_bu = p.K_a_bu; d.K_a_pro = p.K_a_pro; d.K_a_ac = p.K_a_ac;
     d.kLa = p.k_L_a; d.kp = p.k_p_per_V_liq; d.inv_vg = 1.0 / p.V_gas_per_V_liq;
     d.P_atm = p.P_atm;
+    d.inv_P_atm = 1.0 / p.P_atm;
+    d.inv_K_I_nh3 = 1.0 / p.K_I_nh3;
     d.f_sI_xc = p.f_sI_xc; d.f_xI_xc = p.f_xI_xc; d.f_ch_xc = p.f_ch_xc;
     d.f_pr_xc = p.f_pr_xc; d.f_li_xc = p.f_li_xc; d.f_fa_li = p.f_fa_li;
     d.nu5_bu = nu[eSbu][4]; d.nu5_pro = nu[eSpro][4]; d.nu5_ac = nu[eSac][4];

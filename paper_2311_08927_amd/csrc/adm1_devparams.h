@@ -22,6 +22,7 @@ typedef struct DevParams {
     double K_S_IN, eps_c4;
     // pH inhibition (eqs. 3-4, Hill form in S_H+): I = 1 / (1 + (S_H/K)^n)
     double pH_K[3], pH_n[3];  // aa, ac, h2
+    double pH_invK[3];        // 1 / pH_K
     int pH_nint[3];           // n when it is a small integer (1..4), else 0
     int pad0;
     // temperature dependence
@@ -33,6 +34,7 @@ typedef struct DevParams {
     double K_a_va, K_a_bu, K_a_pro, K_a_ac;
     // gas phase: transfer, headspace, valve
     double kLa, kp, inv_vg, P_atm;
+    double inv_P_atm, inv_K_I_nh3;
     // stoichiometry
     double f_sI_xc, f_xI_xc, f_ch_xc, f_pr_xc, f_li_xc, f_fa_li;
     double nu5_bu, nu5_pro, nu5_ac, nu5_h2, Y_su;

@@ -181,9 +181,9 @@ static __device__ __attribute__((noinline)) float pow_ool(float r, float n)
 
 // pH inhibition, eqs. 3-4 written in S_H+: 1 / (1 + (S_H+/K)^n).
 template <typename R>
-__device__ __forceinline__ R inhib_pH(R H, double K, double n, int nint)
+__device__ __forceinline__ R inhib_pH(R H, double invK, double n, int nint)
 {
-    const R r = H * frcp((R)K);
+    const R r = H * (R)invK;
     R rn;
     if (nint == 1) rn = r;
     else if (nint == 2) rn = r * r;
@@ -223,13 +223,13 @@ __device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const
     if (solve_H(p, c, y, H, iters)) return 1;
     const R a = (R)c.arr;
     const R Hr = (R)H;
-    const R I_aa = inhib_pH<R>(Hr, p.pH_K[0], p.pH_n[0], p.pH_nint[0]);
-    const R I_ac = inhib_pH<R>(Hr, p.pH_K[1], p.pH_n[1], p.pH_nint[1]);
-    const R I_h2 = inhib_pH<R>(Hr, p.pH_K[2], p.pH_n[2], p.pH_nint[2]);
+    const R I_aa = inhib_pH<R>(Hr, p.pH_invK[0], p.pH_n[0], p.pH_nint[0]);
+    const R I_ac = inhib_pH<R>(Hr, p.pH_invK[1], p.pH_n[1], p.pH_nint[1]);
+    const R I_h2 = inhib_pH<R>(Hr, p.pH_invK[2], p.pH_n[2], p.pH_nint[2]);
     const R sIN = (R)y[SIN];
     const R I_IN = sIN * frcp(sIN + (R)p.K_S_IN);                       // eq. 6
     const R nh3 = (R)c.K_a_IN * sIN * frcp((R)c.K_a_IN + Hr);
-    const R I_nh3 = frcp((R)1 + nh3 * (R)(1.0 / p.K_I_nh3));            // eq. 5
+    const R I_nh3 = frcp((R)1 + nh3 * (R)p.inv_K_I_nh3);                // eq. 5
     const R I5 = I_aa * I_IN;
 
     R rho[19];
@@ -288,7 +288,7 @@ __device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const
     const R P = (R)c.RT * ((R)y[Gh2] * (R)(1.0 / 16.0) + (R)y[Gch4] * (R)(1.0 / 64.0) +
                            (R)y[Gco2]) + (R)c.p_h2o;
     const R Patm = (R)p.P_atm;
-    const R q = P > Patm ? (R)p.kp * (P - Patm) * P / Patm : (R)0;
+    const R q = P > Patm ? (R)p.kp * (P - Patm) * P * (R)p.inv_P_atm : (R)0;
 
     // eq. 2 assembly
     const R Dr = (R)D;
@@ -357,9 +357,9 @@ __device__ __forceinline__ void partials(const DevParams& p, const TConst& c, co
 {
     const double a = c.arr;
     // pH inhibition: dI/dH = -(n/H) I (1 - I)
-    const double I_aa = inhib_pH<double>(H, p.pH_K[0], p.pH_n[0], p.pH_nint[0]);
-    const double I_ac = inhib_pH<double>(H, p.pH_K[1], p.pH_n[1], p.pH_nint[1]);
-    const double I_h2 = inhib_pH<double>(H, p.pH_K[2], p.pH_n[2], p.pH_nint[2]);
+    const double I_aa = inhib_pH<double>(H, p.pH_invK[0], p.pH_n[0], p.pH_nint[0]);
+    const double I_ac = inhib_pH<double>(H, p.pH_invK[1], p.pH_n[1], p.pH_nint[1]);
+    const double I_h2 = inhib_pH<double>(H, p.pH_invK[2], p.pH_n[2], p.pH_nint[2]);
     const double iH = 1.0 / H;
     const double dI_aa = -p.pH_n[0] * iH * I_aa * (1.0 - I_aa);
     const double dI_ac = -p.pH_n[1] * iH * I_ac * (1.0 - I_ac);

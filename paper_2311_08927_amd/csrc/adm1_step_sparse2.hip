@@ -417,7 +417,7 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
         hs = a.dt - s.t;
         clip = true;
     }
-    const double ih = 1.0 / hs;
+    const double ih = frcp(hs);
     double bv[NP];
     ADM1_SP2_DECL;
     bool ok = true;
@@ -474,7 +474,7 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
                     const DevParams& q = params_at(pp);
                     Partials d;
                     partials(q, c, arg, H0, S0, d);
-                    const double alpha = 1.0 / (kR4Gamma * hs);
+                    const double alpha = ih * (1.0 / kR4Gamma);
                     {
                         const DevParams& p = q;
                         ADM1_SP2_BUILD(alpha, D);
@@ -529,8 +529,8 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
 #pragma unroll
         for (int m = 0; m < NDP; ++m) {
             const double at = odd ? p.atol[kVar1[m]] : p.atol[kVar0[m]];
-            const double sc = at + p.rtol * fmax(fabs(s.y[m]), fabs(y1[m]));
-            e += (bv[m] / sc) * (bv[m] / sc);
+            const double r = bv[m] * frcp(at + p.rtol * fmax(fabs(s.y[m]), fabs(y1[m])));
+            e += r * r;
             fin = fin && isfinite(y1[m]);
         }
         e += swp(e);
