@@ -22,14 +22,21 @@
  * pivoting, one particle at a time.  Threads only split the particle list
  * into equal chunks, as in sec. 4.3.
  */
+#ifndef ORC_COUNTED
 #include <complex.h>
+#endif
 #include <math.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
+/* The scalar of the right-hand side: double complex (the complex step of the
+ * Jacobian), or an operation-counting type supplied by the includer
+ * (count_ops.cpp defines ORC_COUNTED and cx before including this file). */
+#ifndef ORC_COUNTED
 typedef double complex cx;
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* State layout (35 entries).  Concentrations in kg COD/m3, except S_IC,     */
