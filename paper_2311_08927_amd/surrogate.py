@@ -395,3 +395,85 @@ def train(sur: Surrogate, X, Tg, epochs: int, batch: int = 8192, lr: float = 1e-
         if log:
             log(f"epoch {e}: loss {hist[-1]:.4e}")
     return hist
+
+
+def train_on_transitions(ctx, sur: Surrogate, train_data: str = "field", n_transitions: int = 1 << 24,
+                         train_steps: int = 96, epochs: int = 96, train_seed: int = 4,
+                         gas_weight: float = 1.0, calibrate: bool = True, log=None) -> dict:
+    """Train the surrogate on transitions the FP64 integrator generates (ctx):
+    a digester field of seed 5 run as the coupling driver runs it (or the
+    batched population of seed 2), about n_transitions transitions over
+    train_steps coupling steps; particle split 90/5/5 with train_seed; the
+    output biases calibrated on half of the validation rows.  Leaves the
+    trained weights in sur; returns the training record."""
+    import time
+
+    import torch
+    dev = "cuda"
+    n_train = W.pad_ld((n_transitions + train_steps - 1) // train_steps, 64)
+    t0 = time.perf_counter()
+    floor = default_floor()
+    sur.set_weights(init_params(train_seed), identity_norm(floor))
+    if train_data == "field":
+        wt = W.digester_field(n_train, seed=5, steps=train_steps)
+        states, Ds, ok, T = integrate_field_states(ctx, wt, train_steps)
+    else:
+        wt = W.batched_population(n_train, seed=2, steps=train_steps)
+        states, Ds, ok, T = integrate_states(ctx, wt, train_steps)
+    g = np.random.default_rng(train_seed)
+    perm = g.permutation(wt.n)
+    tr = torch.from_numpy(np.sort(perm[: int(0.9 * wt.n)])).to(dev)
+    va = torch.from_numpy(np.sort(perm[int(0.9 * wt.n): int(0.95 * wt.n)])).to(dev)
+    out_weight = np.ones(OUT)
+    out_weight[[8, 9, 32, 33, 34]] = gas_weight
+    norm = fit_norm(sur, states, Ds, T, wt.dt, wt.n, floor, rows=tr, out_weight=out_weight)
+    sur.set_weights(init_params(train_seed), norm)
+    X, Tg = dataset(sur, states, Ds, T, wt.dt, wt.n, rows=tr)
+    keep = ok[:, tr].reshape(-1)
+    X, Tg = X[keep].contiguous(), Tg[keep].contiguous()
+    Xv, Tv = dataset(sur, states, Ds, T, wt.dt, wt.n, rows=va)
+    del states
+    gen_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = train(sur, X, Tg, epochs=epochs, batch=8192, lr=1e-3, seed=train_seed, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    steps = epochs * (X.shape[0] // 8192)
+    shift = np.zeros(OUT)
+    if calibrate:
+        half = Xv.shape[0] // 2
+        shift = calibrate_output_bias(sur, Xv[:half], Tv[:half])
+        Xv, Tv = Xv[half:], Tv[half:]
+    val_mse = float(((sur.forward(Xv)[:, :OUT] - Tv) ** 2).mean())
+    rec = {"data": train_data, "transitions": int(keep.sum()), "particles": int(wt.n),
+           "coupling_steps": train_steps, "epochs": epochs, "steps": steps,
+           "seconds": train_s, "data_seconds": gen_s, "loss_first_last": [hist[0], hist[-1]],
+           "val_mse": val_mse, "output_bias_shift_max": float(np.abs(shift).max()),
+           "train_seed": train_seed, "gas_weight": gas_weight, "calibrated": bool(calibrate)}
+    del X, Tg, Xv, Tv
+    torch.cuda.empty_cache()
+    return rec
+
+
+def save_checkpoint(path: str, sur: Surrogate, record: dict):
+    """Weights (flat FP32 in the ABI's layer order), normalisation and the
+    training record, as a NumPy archive without pickled objects."""
+    import json
+    params, norm = sur.get_weights()
+    nd = norm_dict(norm)
+    np.savez(path, params=np.asarray(params, np.float32), record=np.array(json.dumps(record)),
+             **{k: np.asarray(v) for k, v in nd.items()})
+
+
+def load_checkpoint(path: str):
+    """(params, adm1_mlp_norm, record) of a checkpoint written by
+    save_checkpoint."""
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        params = z["params"].astype(np.float32)
+        norm = make_norm(z["in_mean"], z["in_sd"], z["out_mean"], z["out_sd"], z["floor"])
+        record = json.loads(str(z["record"]))
+    if params.size != NPARAMS:
+        raise ValueError(f"{path}: {params.size} parameters, expected {NPARAMS}")
+    return params, norm, record
