@@ -131,7 +131,9 @@ enum {
     ADM1_VARIANT_DENSE1 = 0,  /* one lane per particle, dense bordered LU, pivoting */
     ADM1_VARIANT_SPARSE1 = 1, /* one lane per particle, static-order sparse LU */
     ADM1_VARIANT_SPARSE2 = 2, /* two lanes per particle, register-resident sparse LU */
-    ADM1_VARIANT_COUNT = 3
+    ADM1_VARIANT_SPARSE1_LDS = 3, /* one lane per particle, static-order sparse LU with the
+                                     matrix in LDS (64 particles and 124 KB per compute unit) */
+    ADM1_VARIANT_COUNT = 4
 };
 
 /* Feed description (device pointers).  D[i]: dilution rate q/V of particle i
@@ -350,6 +352,14 @@ int adm1_jacobian(adm1_ctx *ctx, const double *state, int64_t ld, const double *
  * per SIMD, the most that fit the kernel's 40 KB of LDS per wave).
  * Set by the autotuner after timing the candidates.  Synchronous. */
 int adm1_set_launch(adm1_ctx *ctx, int32_t variant, int32_t blocks_per_cu);
+
+/* Service batching of the persistent step kernel (ADM1_VARIANT_SPARSE2):
+ * pairs whose particle finished its interval wait until `pairs` of the wave
+ * are free (or none is active) and are then written back and restarted
+ * together, a pass the whole wave takes part in (1..32; 0 = the default 4).
+ * Results do not depend on it.  Set by the autotuner.  Synchronous;
+ * ADM1_E_OPTS outside 0..32. */
+int adm1_set_service_batch(adm1_ctx *ctx, int32_t pairs);
 
 /* Order in which the persistent step kernel (ADM1_VARIANT_SPARSE2) takes
  * particles from its work queue.  The particles are independent (sec. 4.3,

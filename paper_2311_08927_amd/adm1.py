@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libadm1.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "adm1.h")
 NX, ND, NLIQ = 35, 28, 26
 
-VARIANT_DENSE1, VARIANT_SPARSE1, VARIANT_SPARSE2 = 0, 1, 2
+VARIANT_DENSE1, VARIANT_SPARSE1, VARIANT_SPARSE2, VARIANT_SPARSE1_LDS = 0, 1, 2, 3
 ERRORS = {0: "ok", -1: "E_NULL", -2: "E_SIZE", -3: "E_NOT_DEVICE", -4: "E_PARAMS",
           -5: "E_OPTS", -6: "E_FEED", -7: "E_NOMEM", -8: "E_VARIANT", -9: "E_DT",
           -10: "E_IO", -11: "E_STATIC"}
@@ -84,6 +84,8 @@ def lib():
         L.adm1_jacobian.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, vp]
         L.adm1_set_launch.restype = ctypes.c_int
         L.adm1_set_launch.argtypes = [vp, i32, i32]
+        L.adm1_set_service_batch.restype = ctypes.c_int
+        L.adm1_set_service_batch.argtypes = [vp, i32]
         L.adm1_set_order.restype = ctypes.c_int
         L.adm1_set_order.argtypes = [vp, i32]
         L.adm1_cost_order.restype = ctypes.c_int
@@ -366,6 +368,10 @@ def adm1_set_launch(ctx: int, variant: int, blocks_per_cu: int = 0):
 
 
 ORDER_INDEX, ORDER_COST = 0, 1
+
+
+def adm1_set_service_batch(ctx: int, pairs: int):
+    _check(lib().adm1_set_service_batch(ctx, int(pairs)), "adm1_set_service_batch")
 
 
 def adm1_set_order(ctx: int, mode: int):

@@ -1,12 +1,17 @@
 """Autotuner of the step kernel's launch configuration.
 
-Times the candidate layouts -- one lane per particle with the sparse LU,
-and two lanes per particle (persistent) at 1-4 resident waves per compute
-unit -- on a seeded sample of the caller's workload, picks the fastest and
-sets it on the context with adm1_set_launch.  Choices are cached in a JSON
-file keyed by GPU architecture, sample size and tolerance, so later runs
-skip the timing.  Timing uses HIP events on the launching stream; every
-candidate runs the same sample from the same start state.
+The design space (one coupling interval of a seeded sample of the caller's
+workload per candidate, timed with HIP events on the launching stream, every
+candidate from the same start state):
+  * lanes per particle and placement of the Newton matrix: one lane with a
+    dense pivoted LU in private memory (ADM1_VARIANT_DENSE1), one lane with
+    the static sparse LU in registers (SPARSE1) or in LDS (SPARSE1_LDS), two
+    lanes with the rows split over the pair in registers (SPARSE2);
+  * for the two-lane persistent kernel, resident waves per compute unit
+    (1-4) and the service batch (pairs restarted together: 1, 2, 4, 8).
+The fastest is set on the context (adm1_set_launch, adm1_set_service_batch),
+so the default step path (opts.variant = -1) uses it.  Choices are cached in
+a JSON file keyed by GPU architecture, sample size, tolerance and tag.
 """
 from __future__ import annotations
 
@@ -17,7 +22,30 @@ import numpy as np
 
 from . import adm1 as A
 
-CANDIDATES = [(A.VARIANT_SPARSE1, 0)] + [(A.VARIANT_SPARSE2, b) for b in (1, 2, 3, 4)]
+# (variant, waves per CU, service batch); 0 = the library default
+CANDIDATES = ([(A.VARIANT_DENSE1, 0, 0), (A.VARIANT_SPARSE1, 0, 0),
+               (A.VARIANT_SPARSE1_LDS, 0, 0)] +
+              [(A.VARIANT_SPARSE2, b, sb) for b in (1, 2, 3, 4) for sb in (1, 2, 4, 8)])
+LABELS = {A.VARIANT_DENSE1: "1 lane, dense LU in private memory",
+          A.VARIANT_SPARSE1: "1 lane, sparse LU in registers",
+          A.VARIANT_SPARSE1_LDS: "1 lane, sparse LU in LDS",
+          A.VARIANT_SPARSE2: "2 lanes, sparse LU rows split over the pair in registers"}
+
+
+def describe(choice) -> dict:
+    v, b, sb = choice
+    d = {"variant": int(v), "layout": LABELS.get(int(v), "?")}
+    if v == A.VARIANT_SPARSE2:
+        d.update(waves_per_cu=int(b) or 4, service_batch=int(sb) or 4)
+    return d
+
+
+def apply(ctx: "A.Context", choice):
+    v, b, sb = (int(c) for c in choice)
+    A.adm1_set_launch(ctx.handle, v, b)
+    A.adm1_set_service_batch(ctx.handle, sb)
+
+
 CACHE = os.environ.get("ADM1_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "adm1_autotune.json"))
 
@@ -46,25 +74,24 @@ def save_cache(d: dict):
 
 
 def autotune(ctx: "A.Context", X, T, D, fidx, S_in, dt, n=None, tag="", repeats=2,
-             candidates=CANDIDATES, use_cache=True) -> dict:
+             candidates=CANDIDATES, use_cache=True, log=None) -> dict:
     """Time the candidates on (X, T, D, fidx, S_in) -- device tensors of the
-    sample -- for one coupling interval each; returns {choice, timings_ms}.
-    X is not modified."""
+    sample -- for one coupling interval each; returns {choice, timings_ms,
+    layout}.  X is not modified."""
     import torch
     n = X.shape[1] if n is None else n
     arch = torch.cuda.get_device_properties(X.device).gcnArchName
     key = _key(arch, n, ctx.opts.rtol, tag)
     cache = load_cache() if use_cache else {}
-    if key in cache:
-        v, b = cache[key]["choice"]
-        A.adm1_set_launch(ctx.handle, v, b)
-        return cache[key]
+    if key in cache and len(cache[key].get("choice", [])) == 3:
+        apply(ctx, cache[key]["choice"])
+        return dict(cache[key], cached=True)
     saved_variant = ctx.opts.variant
     ctx.set_opts(variant=-1)
     timings = {}
     stream = torch.cuda.current_stream()
-    for v, b in candidates:
-        A.adm1_set_launch(ctx.handle, v, b)
+    for cand in candidates:
+        apply(ctx, cand)
         ts = []
         for _ in range(repeats):
             Xw = X.clone()
@@ -77,12 +104,14 @@ def autotune(ctx: "A.Context", X, T, D, fidx, S_in, dt, n=None, tag="", repeats=
             e1.record(stream)
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
-        timings[f"{v}:{b}"] = float(np.median(ts))
+        timings[":".join(map(str, cand))] = float(np.median(ts))
+        if log:
+            log(f"# autotune {cand}: {timings[':'.join(map(str, cand))]:.2f} ms")
     best = min(timings, key=timings.get)
-    v, b = (int(t) for t in best.split(":"))
-    A.adm1_set_launch(ctx.handle, v, b)
+    choice = [int(t) for t in best.split(":")]
+    apply(ctx, choice)
     ctx.set_opts(variant=saved_variant)
-    out = {"choice": [v, b], "timings_ms": timings}
+    out = {"choice": choice, "layout": describe(choice), "timings_ms": timings}
     if use_cache:
         cache[key] = out
         save_cache(cache)

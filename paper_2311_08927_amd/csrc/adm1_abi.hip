@@ -443,15 +443,19 @@ int step_dispatch(adm1_ctx* ctx, const StepScratch& w, double* state, int64_t ld
     a.hlast = aux ? aux->h_last : nullptr;
     a.status = status; a.nsteps = nsteps; a.queue = w.queue;
     a.pdev = ctx->d_params;
+    a.service_batch = ctx->tuned_service_batch;
     int variant = ctx->opts.variant;
     if (variant < 0) variant = ctx->tuned_variant >= 0 ? ctx->tuned_variant : ADM1_VARIANT_SPARSE2;
     int rc = ADM1_OK;
     switch (variant) {
     case ADM1_VARIANT_DENSE1:
-        rc = hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, false, s));
+        rc = hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, 0, s));
         break;
     case ADM1_VARIANT_SPARSE1:
-        rc = hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, true, s));
+        rc = hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, 1, s));
+        break;
+    case ADM1_VARIANT_SPARSE1_LDS:
+        rc = hip_rc(adm1::launch_step1(a, ctx->opts.rate_precision, 2, s));
         break;
     case ADM1_VARIANT_SPARSE2:
         // expensive particles first (predicted by the previous interval's
@@ -656,6 +660,14 @@ int adm1_set_launch(adm1_ctx* ctx, int32_t variant, int32_t blocks_per_cu)
     return ADM1_OK;
 }
 
+
+int adm1_set_service_batch(adm1_ctx* ctx, int32_t pairs)
+{
+    if (!ctx) return ADM1_E_NULL;
+    if (pairs < 0 || pairs > 32) return ADM1_E_OPTS;
+    ctx->tuned_service_batch = pairs;
+    return ADM1_OK;
+}
 
 int adm1_graph_capture_step(adm1_ctx* ctx, double* state, int64_t ld, const double* temp_K,
                             const adm1_feed* feed, double dt_days, int64_t n, adm1_aux* aux,

@@ -18,6 +18,7 @@ struct adm1_ctx {
     adm1::DevParams* d_params;  // device copy of dp
     int tuned_variant;   // step variant chosen by adm1_set_launch (-1: none)
     int tuned_blocks_per_cu;
+    int tuned_service_batch;  // pairs served together by the persistent kernel (0: default)
     int order_mode;      // ADM1_ORDER_* of the step kernel's work queue
     int32_t* d_order;    // cost-ordered particle list [max(n_max, 1)]
     int32_t* d_order_work;  // its histogram, bucket cursors and length

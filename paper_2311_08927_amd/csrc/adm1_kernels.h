@@ -26,6 +26,7 @@ struct StepArgs {
     const int32_t* index_count;  // device count of the index list (with index)
     int64_t index_bound;    // host upper bound of that count (0: unknown)
     const DevParams* pdev;  // device copy of p (read through the scalar cache)
+    int32_t service_batch;  // persistent kernel: pairs served together (0: default)
 };
 
 struct RhsArgs {
@@ -54,7 +55,9 @@ struct GasArgs {
     double* partial;  // [nblocks][4]
 };
 
-hipError_t launch_step1(const StepArgs& a, int rate_precision, bool sparse, hipStream_t s);
+// One lane per particle; lin: 0 dense pivoted LU (private memory), 1 static
+// sparse LU in registers, 2 static sparse LU with the matrix in LDS.
+hipError_t launch_step1(const StepArgs& a, int rate_precision, int lin, hipStream_t s);
 hipError_t launch_step_sparse2(const StepArgs& a, int rate_precision, int blocks_per_cu,
                                hipStream_t s);
 // Cost order of the work queue: order[0..len-1] = particles by non-increasing

@@ -137,6 +137,33 @@ struct LinSparse1 {  // generated static-order sparse LU, named scalars
     __device__ void solve(double* b) const { ADM1_SP_SOLVE(b); }
 };
 
+#include "adm1_jac_sparse1_lds.inc"
+
+// The LDS of the one-lane kernel with the matrix in LDS: ADM1_SPL_NNZ
+// entries of each of the 64 particles of the workgroup (124 KB; one
+// workgroup per compute unit).
+__device__ __forceinline__ double* lds_lu()
+{
+    __shared__ double buf[ADM1_SPL_NNZ * 64];
+    return buf;
+}
+
+struct LinSparse1Lds {  // generated static-order sparse LU, matrix in LDS
+    double* Lm;  // this lane's entry 0; entry e at Lm[e * 64]
+    ADM1_SPL_DECL
+    __device__ LinSparse1Lds() : Lm(lds_lu() + threadIdx.x) {}
+#define ADM1_SPL_M(e) Lm[(e) * 64]
+    __device__ bool setup(const DevParams& p, const Partials& d, double alpha, double D)
+    {
+        ADM1_SPL_BUILD(alpha, D);
+        bool ok = true;
+        ADM1_SPL_FACTOR(ok);
+        return ok;
+    }
+    __device__ void solve(double* b) const { ADM1_SPL_SOLVE(b); }
+#undef ADM1_SPL_M
+};
+
 // One coupling interval for one particle on one lane.
 template <typename R, typename Lin>
 __device__ static int integrate1(const DevParams& p, const TConst& c, double* y, double D,
@@ -581,20 +608,22 @@ __global__ void __launch_bounds__(256) k_gasflux_final(const double* partial, in
 // ---------------------------------------------------------------------------
 // Launchers (host)
 // ---------------------------------------------------------------------------
-hipError_t launch_step1(const StepArgs& a, int rate_precision, bool sparse, hipStream_t s)
+hipError_t launch_step1(const StepArgs& a, int rate_precision, int lin, hipStream_t s)
 {
     const unsigned grid = (unsigned)((a.n + 63) / 64);
     if (grid == 0) return hipSuccess;
-    if (sparse) {
-        if (rate_precision)
-            hipLaunchKernelGGL((k_step1<float, LinSparse1>), dim3(grid), dim3(64), 0, s, a);
+    const bool f32 = rate_precision != 0;
+    if (lin == 1) {
+        if (f32) hipLaunchKernelGGL((k_step1<float, LinSparse1>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_step1<double, LinSparse1>), dim3(grid), dim3(64), 0, s, a);
+    } else if (lin == 2) {
+        if (f32)
+            hipLaunchKernelGGL((k_step1<float, LinSparse1Lds>), dim3(grid), dim3(64), 0, s, a);
         else
-            hipLaunchKernelGGL((k_step1<double, LinSparse1>), dim3(grid), dim3(64), 0, s, a);
+            hipLaunchKernelGGL((k_step1<double, LinSparse1Lds>), dim3(grid), dim3(64), 0, s, a);
     } else {
-        if (rate_precision)
-            hipLaunchKernelGGL((k_step1<float, LinDense>), dim3(grid), dim3(64), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_step1<double, LinDense>), dim3(grid), dim3(64), 0, s, a);
+        if (f32) hipLaunchKernelGGL((k_step1<float, LinDense>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_step1<double, LinDense>), dim3(grid), dim3(64), 0, s, a);
     }
     return hipGetLastError();
 }

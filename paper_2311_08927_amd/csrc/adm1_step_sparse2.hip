@@ -45,7 +45,7 @@ constexpr int kVarPair[NP * 2] = ADM1_SP2_VAR_PAIR;
 constexpr int kVarSide[NP * 2] = ADM1_SP2_VAR_SIDE;
 constexpr int kWavesPerCU = 4;  // one wave per SIMD: 4 x 40 KB of LDS per CU
 constexpr int kStored = 4;      // stage vectors kept in LDS (see the header)
-constexpr int kServiceBatch = 4;  // pairs served per service pass
+constexpr int kServiceBatch = 4;  // pairs served per service pass (default)
 static_assert(kR4Stages == 6, "the stage-5 accumulation assumes six stages");
 
 static_assert(kVar0[NP - 1] == 28 && kVar1[NP - 1] == 29,
@@ -580,12 +580,14 @@ __global__ void __launch_bounds__(64, 1) k_step_sparse2(StepArgs a)
     s.pid = -1;
     bool active = false, exhausted = false;
     int job = kNone, fin_status = 0;
+    const int batch = a.service_batch > 0 ? (a.service_batch < 32 ? a.service_batch : 32)
+                                          : kServiceBatch;
     for (;;) {
         // pairs waiting for service (finished particles, free pairs with work
         // left) are served together: a service pass costs the whole wave
         const bool waiting = !active && (job != kNone || !exhausted);
         const int nwait = __popcll(__ballot(waiting && !odd));
-        if (nwait >= kServiceBatch || !__any(active))
+        if (nwait >= batch || !__any(active))
             service<R>(a, pp, L, s, job, fin_status, active, exhausted, odd, lane, total);
         if (__all(exhausted)) break;
         if (active) {

@@ -621,6 +621,7 @@ int adm1_surrogate_step(adm1_surrogate* s, double* state, int64_t ld, const doub
     a.status = status; a.nsteps = nsteps; a.queue = ctx->d_queue;
     a.index = s->fb_idx; a.index_count = cnt;
     a.pdev = ctx->d_params;
+    a.service_batch = ctx->tuned_service_batch;
     // the fallback list in expected-cost order, as the full step orders its
     // queue (rejected particles are the stiff ones: the tail matters most)
     if (ctx->order_mode == ADM1_ORDER_COST && a.hlast) {

@@ -14,9 +14,13 @@ structure and emits:
 
   adm1_jac_dense.inc  -- fills a dense row-major M[30*30] (one lane per
                          particle, partial pivoting);
-  adm1_jac_sparse.inc -- the two-lanes-per-particle kernel body pieces: the
+  adm1_jac_sparse1.inc -- one lane per particle: the static-order sparse LU
+                         in named registers (emit_sparse1);
+  adm1_jac_sparse1_lds.inc -- the same LU with the matrix in LDS
+                         (emit_sparse1_lds);
+  adm1_jac_sparse2.inc -- the two-lanes-per-particle kernel body pieces: the
                          static-order sparse LU, with rows split over a lane
-                         pair (see emit_sparse).
+                         pair (see emit_sparse2).
 
 Run: python gen_jac.py   (writes the .inc files next to this script)
 """
@@ -274,6 +278,48 @@ def emit_sparse1():
     return "\n".join(out) + "\n"
 
 
+def emit_sparse1_lds():
+    """One lane per particle with the bordered matrix in LDS: entry e of the
+    static-order LU (the 242 positions of emit_sparse1, in sorted order) of
+    the lane's particle at ADM1_SPL_M(e), which the kernel maps to
+    lds[e * 64 + lane] (consecutive lanes, consecutive banks); the inverse
+    pivots stay in registers.  Same arithmetic as emit_sparse1."""
+    order, cur, L, U = analyze()
+    M = entries()
+    names = sorted(cur)
+    idx = {rc: e for e, rc in enumerate(names)}
+    m = lambda r, c: f"ADM1_SPL_M({idx[(r, c)]})"  # noqa: E731
+    out = ["// Generated by gen_jac.py: sparse bordered Newton matrix in LDS, static-order LU.",
+           f"// structural nonzeros {len(M)}, with fill {len(cur)}",
+           f"#define ADM1_SPL_NNZ {len(cur)}",
+           "#define ADM1_SPL_DECL \\",
+           "    double " + ", ".join(f"iv_{k}" for k in range(NV)) + ";",
+           "#define ADM1_SPL_BUILD(alpha, D) \\"]
+    for (r, c) in names:
+        e = expr(M[(r, c)], c) if (r, c) in M else "0.0"
+        e = e.replace("alpha", "(alpha)").replace("(alpha + D)", "((alpha) + (D))")
+        out.append(f"    {m(r, c)} = {e}; \\")
+    out.append("    (void)0")
+    out.append("#define ADM1_SPL_FACTOR(ok) \\")
+    for k in order:
+        out.append(f"    iv_{k} = 1.0 / {m(k, k)}; ok = ok && isfinite(iv_{k}); \\")
+        for i in L[k]:
+            out.append(f"    {m(i, k)} *= iv_{k}; \\")
+        for i in L[k]:
+            for j in U[k]:
+                out.append(f"    {m(i, j)} -= {m(i, k)} * {m(k, j)}; \\")
+    out.append("    (void)0")
+    out.append("#define ADM1_SPL_SOLVE(b) \\")
+    for k in order:
+        for i in L[k]:
+            out.append(f"    b[{i}] -= {m(i, k)} * b[{k}]; \\")
+    for k in reversed(order):
+        terms = "".join(f" - {m(k, j)} * b[{j}]" for j in U[k])
+        out.append(f"    b[{k}] = (b[{k}]{terms}) * iv_{k}; \\")
+    out.append("    (void)0")
+    return "\n".join(out) + "\n"
+
+
 def pairing(order, cur):
     """Rows (elimination positions) paired over the two lanes of a particle.
     The two constraint rows form the last pair; the others are paired greedily,
@@ -478,6 +524,8 @@ def main():
         fh.write(emit_dense())
     with open(os.path.join(HERE, "adm1_jac_sparse1.inc"), "w") as fh:
         fh.write(emit_sparse1())
+    with open(os.path.join(HERE, "adm1_jac_sparse1_lds.inc"), "w") as fh:
+        fh.write(emit_sparse1_lds())
     stats = lu_counts()
     stats["assembly_flops"] = assembly_flops()
     import json

@@ -40,7 +40,7 @@ def make_ctx(n_max, variant=None, rate_precision=0):
                    **kw)
 
 
-VARIANTS = [0, 1, 2]
+VARIANTS = [0, 1, 2, 3]
 
 
 # ---------------------------------------------------------------------------

@@ -83,7 +83,13 @@ def test_autotune_and_launch_setting(torch_cuda, tmp_path, monkeypatch):
     res = AT.autotune(ctx, dw.X, dw.T, dw.D, dw.fidx, dw.S_in, w.dt, n=w.n, tag="test")
     assert tuple(res["choice"]) in [tuple(c) for c in AT.CANDIDATES]
     assert len(res["timings_ms"]) == len(AT.CANDIDATES)
-    print("autotune:", res)
+    # the space: lanes per particle 1 and 2; the Newton matrix in private
+    # memory, registers or LDS; waves per CU 1-4; service batches 1-8
+    assert {c[0] for c in AT.CANDIDATES} == {A.VARIANT_DENSE1, A.VARIANT_SPARSE1,
+                                             A.VARIANT_SPARSE1_LDS, A.VARIANT_SPARSE2}
+    assert {c[1] for c in AT.CANDIDATES if c[0] == A.VARIANT_SPARSE2} == {1, 2, 3, 4}
+    assert {c[2] for c in AT.CANDIDATES if c[0] == A.VARIANT_SPARSE2} == {1, 2, 4, 8}
+    print("autotune:", res["layout"], {k: round(v, 2) for k, v in res["timings_ms"].items()})
     # cached second call
     res2 = AT.autotune(ctx, dw.X, dw.T, dw.D, dw.fidx, dw.S_in, w.dt, n=w.n, tag="test")
     assert res2["choice"] == res["choice"]
@@ -99,7 +105,29 @@ def test_autotune_and_launch_setting(torch_cuda, tmp_path, monkeypatch):
         A.adm1_set_launch(ctx.handle, 7, 0)
     with pytest.raises(A.ADM1Error):
         A.adm1_set_launch(ctx.handle, A.VARIANT_SPARSE2, 9)
+    with pytest.raises(A.ADM1Error):
+        A.adm1_set_service_batch(ctx.handle, 33)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("batch", [1, 8, 32])
+def test_service_batch_does_not_change_results(torch_cuda, batch):
+    """Restarting particles in batches of any size gives the same results
+    (bit for bit) as the default batch, cold and warm intervals."""
+    from paper_2311_08927_amd import adm1 as A
+    w = W.batched_population(3000, seed=10)
+    outs = []
+    for sb in (0, batch):
+        ctx = make_ctx(w.ld, variant=A.VARIANT_SPARSE2)
+        A.adm1_set_service_batch(ctx.handle, sb)
+        d = DeviceWorkload(w)
+        for k in range(2):
+            d.set_D(w.D_at(k))
+            ctx.step(d.X, d.T, d.D, d.fidx, d.S_in, w.dt, n=w.n, H=d.H, hlast=d.hlast,
+                     nsteps=d.nsteps)
+        outs.append((d.X.cpu().numpy(), d.nsteps.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
 
 
 @pytest.mark.parametrize("blocks", [1, 3])
