@@ -577,6 +577,12 @@ void adm1_surrogate_destroy(adm1_surrogate *s);
 /* Comma-separated adm1_params field names in struct order (static string). */
 const char *adm1_param_names(void);
 
+/* Name of the model description this library was generated from (sec. 2.2,
+ * eq. 2: the Petersen matrix as data; static string): "adm1" for the
+ * standard matrix.  The matrix's sparsity is compiled into the kernels, so
+ * each description is its own library. */
+const char *adm1_model_name(void);
+
 /* Human-readable name of an ADM1_E* or HIP error code (static string). */
 const char *adm1_strerror(int code);
 

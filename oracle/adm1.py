@@ -52,6 +52,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_param_names.restype = ctypes.c_char_p
         L.orc_param_count.restype = ctypes.c_int
+        L.orc_params_doubles.restype = ctypes.c_int
         L.orc_check_params.restype = ctypes.c_int
         L.orc_run.restype = ctypes.c_int
         L.orc_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_int64, dp, dp,
@@ -112,7 +113,7 @@ class Oracle:
 
     def __init__(self, params: dict | str | None = None, rtol: float = 1e-8,
                  atol=None, max_steps: int = 100000, newton_tol: float = 1e-14,
-                 newton_maxit: int = 100):
+                 newton_maxit: int = 100, model: str | None = None):
         if params is None or isinstance(params, str):
             with open(params or DEFAULT_PARAMS) as fh:
                 params = json.load(fh)["values"]
@@ -120,7 +121,18 @@ class Oracle:
         L = lib()
         names = L.orc_param_names().decode().split(",")[:-1]
         assert len(names) == L.orc_param_count()
-        self._p = (ctypes.c_double * len(names))(*[float(self.values[n]) for n in names])
+        size = L.orc_params_doubles()
+        assert size == len(names) + NLIQ * NPROC + 2 * NLIQ + 1
+        self._p = (ctypes.c_double * size)(*[float(self.values[n]) for n in names])
+        self.model = model
+        if model is not None:
+            # the description's matrix and contents, by the oracle's own reader
+            from oracle import model_desc
+            nu, C, N = model_desc.tables(model_desc.load(model), self.values)
+            base = len(names)
+            flat = np.concatenate([nu.ravel(), C, N, [1.0]])
+            for k, v in enumerate(flat):
+                self._p[base + k] = float(v)
         if L.orc_check_params(ctypes.byref(self._p)) != 0:
             raise ValueError("parameter set violates COD continuity")
         if atol is None:

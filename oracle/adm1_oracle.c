@@ -91,6 +91,13 @@ typedef struct {
 #define ORC_DECL(n) double n;
     ORC_PARAMS(ORC_DECL)
 #undef ORC_DECL
+    /* A model description's Petersen matrix (organic rows; the S_IC and S_IN
+     * rows are closures) and carbon / nitrogen contents, evaluated by the
+     * binding from the description file; used instead of the built-in
+     * standard ADM1 formulas below when model_set is nonzero. */
+    double model_nu[NLIQ][NPROC];
+    double model_C[NLIQ], model_N[NLIQ];
+    double model_set;
 } orc_params;
 
 static const char orc_names[] =
@@ -100,7 +107,13 @@ static const char orc_names[] =
     ;
 
 const char *orc_param_names(void) { return orc_names; }
-int orc_param_count(void) { return (int)(sizeof(orc_params) / sizeof(double)); }
+#define ORC_ONE(n) +1
+int orc_param_count(void) { return 0 ORC_PARAMS(ORC_ONE); }
+#undef ORC_ONE
+/* size of the parameter block in doubles; the model fields follow the named
+ * parameters: model_nu at orc_param_count(), then model_C, model_N,
+ * model_set */
+int orc_params_doubles(void) { return (int)(sizeof(orc_params) / sizeof(double)); }
 
 /* Integration options (sec. 2.3 leaves them open; see the readings). */
 typedef struct {
@@ -153,6 +166,10 @@ void orc_tconst_export(const orc_params *p, double T, double out[9])
 /* ------------------------------------------------------------------------ */
 static void carbon_nitrogen(const orc_params *p, double C[NLIQ], double N[NLIQ])
 {
+    if (p->model_set != 0.0) {
+        for (int i = 0; i < NLIQ; i++) { C[i] = p->model_C[i]; N[i] = p->model_N[i]; }
+        return;
+    }
     for (int i = 0; i < NLIQ; i++) { C[i] = 0.0; N[i] = 0.0; }
     C[S_SU] = p->C_su; C[S_AA] = p->C_aa; C[S_FA] = p->C_fa; C[S_VA] = p->C_va;
     C[S_BU] = p->C_bu; C[S_PRO] = p->C_pro; C[S_AC] = p->C_ac; C[S_CH4] = p->C_ch4;
@@ -167,6 +184,10 @@ static void carbon_nitrogen(const orc_params *p, double C[NLIQ], double N[NLIQ])
 static void petersen(const orc_params *p, double nu[NLIQ][NPROC])
 {
     memset(nu, 0, sizeof(double) * NLIQ * NPROC);
+    if (p->model_set != 0.0) {
+        memcpy(nu, p->model_nu, sizeof(double) * NLIQ * NPROC);
+        goto closures;
+    }
     /* 1 disintegration */
     nu[X_XC][0] = -1.0; nu[S_I][0] = p->f_sI_xc; nu[X_CH][0] = p->f_ch_xc;
     nu[X_PR][0] = p->f_pr_xc; nu[X_LI][0] = p->f_li_xc; nu[X_I][0] = p->f_xI_xc;
@@ -217,6 +238,7 @@ static void petersen(const orc_params *p, double nu[NLIQ][NPROC])
     /* 13-19 decay of the seven biomasses into composites */
     for (int b = 0; b < 7; b++) { nu[X_SU + b][12 + b] = -1.0; nu[X_XC][12 + b] = 1.0; }
 
+closures:;
     /* carbon and nitrogen closure: inorganic C and N take up whatever the
      * organic entries release, so C and N are conserved by every process */
     double C[NLIQ], N[NLIQ];

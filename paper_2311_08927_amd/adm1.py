@@ -24,7 +24,8 @@ ERRORS = {0: "ok", -1: "E_NULL", -2: "E_SIZE", -3: "E_NOT_DEVICE", -4: "E_PARAMS
           -5: "E_OPTS", -6: "E_FEED", -7: "E_NOMEM", -8: "E_VARIANT", -9: "E_DT",
           -10: "E_IO", -11: "E_STATIC"}
 
-_lib = None
+_libs: dict = {}     # library path -> loaded library
+_owner: dict = {}    # context / graph handle -> the library that created it
 
 
 class ADM1Error(RuntimeError):
@@ -49,14 +50,23 @@ class adm1_aux(ctypes.Structure):
     _fields_ = [("H", ctypes.c_void_p), ("h_last", ctypes.c_void_p)]
 
 
-def lib():
-    """Load libadm1.so (raises if it has not been built)."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: the HIP extension is not built "
+def lib_path(model: str | None = None) -> str:
+    """Library of a model description by name: lib<model>.so (None or "adm1":
+    libadm1.so, the standard matrix)."""
+    if model is None or model == "adm1":
+        return LIB_PATH
+    return os.path.join(PKG, f"lib{model}.so")
+
+
+def lib(model: str | None = None):
+    """Load the library of a model description (default: the standard ADM1
+    matrix, libadm1.so); raises if it has not been built."""
+    path = lib_path(model)
+    if path not in _libs:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: the HIP extension is not built "
                                "(run __graft_entry__.build())")
-        L = ctypes.CDLL(LIB_PATH)
+        L = ctypes.CDLL(path)
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.adm1_param_names.restype = ctypes.c_char_p
         L.adm1_strerror.restype = ctypes.c_char_p
@@ -105,8 +115,22 @@ def lib():
         L.adm1_grid_destroy.argtypes = [vp]
         L.adm1_diffuse.restype = ctypes.c_int
         L.adm1_diffuse.argtypes = [vp, vp, i64, vp, i64, dbl, i32, vp, vp]
-        _lib = L
-    return _lib
+        L.adm1_model_name.restype = ctypes.c_char_p
+        want = "adm1" if model is None else model
+        got = L.adm1_model_name().decode()
+        if got != want:
+            raise RuntimeError(f"{path} was generated from model {got!r}, not {want!r}")
+        _libs[path] = L
+    return _libs[path]
+
+
+def _L(handle):
+    """The library that created a context or graph handle."""
+    return _owner.get(handle) or lib()
+
+
+def model_name(ctx) -> str:
+    return _L(ctx).adm1_model_name().decode()
 
 
 def strerror(code: int) -> str:
@@ -166,27 +190,31 @@ def feed_struct(D, idx, S_in) -> adm1_feed:
 # ---------------------------------------------------------------------------
 # C-named entry points
 # ---------------------------------------------------------------------------
-def adm1_init(params, opts: adm1_opts, n_max: int) -> int:
-    """Create a context; returns the opaque handle (int)."""
+def adm1_init(params, opts: adm1_opts, n_max: int, model: str | None = None) -> int:
+    """Create a context in the library of `model` (default: the standard
+    matrix); returns the opaque handle (int)."""
     if isinstance(params, dict):
         params = make_params(params)
     h = ctypes.c_void_p()
-    _check(lib().adm1_init(ctypes.byref(params), ctypes.byref(opts), int(n_max),
-                           ctypes.byref(h)), "adm1_init")
+    L = lib(model)
+    _check(L.adm1_init(ctypes.byref(params), ctypes.byref(opts), int(n_max),
+                       ctypes.byref(h)), "adm1_init")
+    _owner[h.value] = L
     return h.value
 
 
 def adm1_set_opts(ctx: int, opts: adm1_opts):
-    _check(lib().adm1_set_opts(ctx, ctypes.byref(opts)), "adm1_set_opts")
+    _check(_L(ctx).adm1_set_opts(ctx, ctypes.byref(opts)), "adm1_set_opts")
 
 
 def adm1_destroy(ctx: int):
-    lib().adm1_destroy(ctx)
+    _L(ctx).adm1_destroy(ctx)
+    _owner.pop(ctx, None)
 
 
 def adm1_step_particles(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, n, aux=None,
                         status=None, nsteps=None, stream=None, check=True) -> int:
-    rc = lib().adm1_step_particles(ctx, _ptr(state), int(ld), _ptr(temp_K),
+    rc = _L(ctx).adm1_step_particles(ctx, _ptr(state), int(ld), _ptr(temp_K),
                                    ctypes.byref(feed), float(dt_days), int(n),
                                    None if aux is None else ctypes.byref(aux), _ptr(status),
                                    _ptr(nsteps), _stream(stream))
@@ -202,7 +230,7 @@ def adm1_step_particles_static(ctx, state, ld, temp_K, feed: adm1_feed, dt_days,
                                status=None, nsteps=None, stream=None, check=True) -> int:
     """adm1_step_particles with the work buffers in the library's static
     device array (no allocation; n <= STATIC_MAX_N)."""
-    rc = lib().adm1_step_particles_static(ctx, _ptr(state), int(ld), _ptr(temp_K),
+    rc = _L(ctx).adm1_step_particles_static(ctx, _ptr(state), int(ld), _ptr(temp_K),
                                           ctypes.byref(feed), float(dt_days), int(n),
                                           None if aux is None else ctypes.byref(aux),
                                           _ptr(status), _ptr(nsteps), _stream(stream))
@@ -216,7 +244,7 @@ FIXED_EULER, FIXED_RK4 = 0, 1
 
 def adm1_step_fixed(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, substeps, method, n,
                     H=None, status=None, newton=None, stream=None, check=True) -> int:
-    rc = lib().adm1_step_fixed(ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed),
+    rc = _L(ctx).adm1_step_fixed(ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed),
                                float(dt_days), int(substeps), int(method), int(n), _ptr(H),
                                _ptr(status), _ptr(newton), _stream(stream))
     if check:
@@ -226,7 +254,7 @@ def adm1_step_fixed(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, substeps, 
 
 def adm1_gas_flux(ctx, state, ld, temp_K, V_liq, n, q_gas, q_ch4, totals, stream=None,
                   check=True) -> int:
-    rc = lib().adm1_gas_flux(ctx, _ptr(state), int(ld), _ptr(temp_K), _ptr(V_liq), int(n),
+    rc = _L(ctx).adm1_gas_flux(ctx, _ptr(state), int(ld), _ptr(temp_K), _ptr(V_liq), int(n),
                              _ptr(q_gas), _ptr(q_ch4), _ptr(totals), _stream(stream))
     if check:
         _check(rc, "adm1_gas_flux")
@@ -235,7 +263,7 @@ def adm1_gas_flux(ctx, state, ld, temp_K, V_liq, n, q_gas, q_ch4, totals, stream
 
 def adm1_rhs(ctx, state, ld, temp_K, feed: adm1_feed, n, dxdt, ld_out, H_out=None,
              rate_precision=0, status=None, stream=None, check=True) -> int:
-    rc = lib().adm1_rhs(ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed), int(n),
+    rc = _L(ctx).adm1_rhs(ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed), int(n),
                         _ptr(dxdt), int(ld_out), _ptr(H_out), int(rate_precision),
                         _ptr(status), _stream(stream))
     if check:
@@ -245,7 +273,7 @@ def adm1_rhs(ctx, state, ld, temp_K, feed: adm1_feed, n, dxdt, ld_out, H_out=Non
 
 def adm1_solve_ph(ctx, state, ld, temp_K, n, H_guess, H_out, pH_out=None, status=None,
                   stream=None, check=True) -> int:
-    rc = lib().adm1_solve_ph(ctx, _ptr(state), int(ld), _ptr(temp_K), int(n), _ptr(H_guess),
+    rc = _L(ctx).adm1_solve_ph(ctx, _ptr(state), int(ld), _ptr(temp_K), int(n), _ptr(H_guess),
                              _ptr(H_out), _ptr(pH_out), _ptr(status), _stream(stream))
     if check:
         _check(rc, "adm1_solve_ph")
@@ -260,13 +288,13 @@ FAIL_NAMES = ["failed", "algebraic", "underflow", "max_steps", "nonfinite", "neg
 def adm1_last_failures(ctx, stream=None) -> dict:
     """Outcome counts of the last step call (synchronous)."""
     out = (ctypes.c_int64 * FAIL_SLOTS)()
-    _check(lib().adm1_last_failures(ctx, out, _stream(stream)), "adm1_last_failures")
+    _check(_L(ctx).adm1_last_failures(ctx, out, _stream(stream)), "adm1_last_failures")
     return dict(zip(FAIL_NAMES, [int(v) for v in out]))
 
 
 def adm1_jacobian(ctx, state, ld, temp_K, feed: adm1_feed, n, J, status=None, stream=None,
                   check=True) -> int:
-    rc = lib().adm1_jacobian(ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed),
+    rc = _L(ctx).adm1_jacobian(ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed),
                              int(n), _ptr(J), _ptr(status), _stream(stream))
     if check:
         _check(rc, "adm1_jacobian")
@@ -364,42 +392,44 @@ def adm1_feed_mask(pos, ld, n, z_min, r_max, D_zone, fidx_zone, fidx_out, D, fid
 
 
 def adm1_set_launch(ctx: int, variant: int, blocks_per_cu: int = 0):
-    _check(lib().adm1_set_launch(ctx, int(variant), int(blocks_per_cu)), "adm1_set_launch")
+    _check(_L(ctx).adm1_set_launch(ctx, int(variant), int(blocks_per_cu)), "adm1_set_launch")
 
 
 ORDER_INDEX, ORDER_COST = 0, 1
 
 
 def adm1_set_service_batch(ctx: int, pairs: int):
-    _check(lib().adm1_set_service_batch(ctx, int(pairs)), "adm1_set_service_batch")
+    _check(_L(ctx).adm1_set_service_batch(ctx, int(pairs)), "adm1_set_service_batch")
 
 
 def adm1_set_order(ctx: int, mode: int):
-    _check(lib().adm1_set_order(ctx, int(mode)), "adm1_set_order")
+    _check(_L(ctx).adm1_set_order(ctx, int(mode)), "adm1_set_order")
 
 
 def adm1_cost_order(ctx: int, h_last, dt_days, n, order, stream=None):
-    _check(lib().adm1_cost_order(ctx, _ptr(h_last), float(dt_days), int(n), _ptr(order),
+    _check(_L(ctx).adm1_cost_order(ctx, _ptr(h_last), float(dt_days), int(n), _ptr(order),
                                  _stream(stream)), "adm1_cost_order")
 
 
 def adm1_graph_capture_step(ctx, state, ld, temp_K, feed: adm1_feed, dt_days, n, aux, status,
                             nsteps, V_liq, q_gas, q_ch4, totals, stream) -> int:
     g = ctypes.c_void_p()
-    _check(lib().adm1_graph_capture_step(
+    _check(_L(ctx).adm1_graph_capture_step(
         ctx, _ptr(state), int(ld), _ptr(temp_K), ctypes.byref(feed), float(dt_days), int(n),
         None if aux is None else ctypes.byref(aux), _ptr(status), _ptr(nsteps), _ptr(V_liq),
         _ptr(q_gas), _ptr(q_ch4), _ptr(totals), _stream(stream), ctypes.byref(g)),
         "adm1_graph_capture_step")
+    _owner[g.value] = _L(ctx)
     return g.value
 
 
 def adm1_graph_launch(g: int, stream=None):
-    _check(lib().adm1_graph_launch(g, _stream(stream)), "adm1_graph_launch")
+    _check(_L(g).adm1_graph_launch(g, _stream(stream)), "adm1_graph_launch")
 
 
 def adm1_graph_destroy(g: int):
-    lib().adm1_graph_destroy(g)
+    _L(g).adm1_graph_destroy(g)
+    _owner.pop(g, None)
 
 
 # ---------------------------------------------------------------------------
@@ -408,11 +438,13 @@ def adm1_graph_destroy(g: int):
 class Context:
     """Owns an adm1 context; methods take torch CUDA tensors."""
 
-    def __init__(self, n_max: int, rtol: float = 1e-8, atol=None, params=None, **opt_kw):
+    def __init__(self, n_max: int, rtol: float = 1e-8, atol=None, params=None,
+                 model: str | None = None, **opt_kw):
         self.values = params if isinstance(params, dict) else load_params(params)
         self.opts = make_opts(rtol=rtol, atol=atol, **opt_kw)
-        self.handle = adm1_init(make_params(self.values), self.opts, n_max)
+        self.handle = adm1_init(make_params(self.values), self.opts, n_max, model=model)
         self.n_max = n_max
+        self.model = model_name(self.handle)
 
     def set_opts(self, **kw):
         cur = dict(rtol=self.opts.rtol, atol=np.array(self.opts.atol),

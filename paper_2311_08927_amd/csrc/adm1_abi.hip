@@ -97,35 +97,16 @@ enum E {
     eXpr, eXli, eXsu, eXaa, eXfa, eXc4, eXpro, eXac, eXh2, eXI, eScat, eSan, eNLIQ
 };
 
+#include <adm1_stoich.inc>
+static_assert(ADM1_NU_COUNT <= ADM1_NU_MAX, "coefficient table of the model description");
+
 // Petersen matrix of eq. 2 (organic entries; the inorganic C and N rows are
-// derived as closures) built from the named parameters.
+// derived as closures) from the named parameters, as the model description
+// states it (generated).
 void petersen(const adm1_params& p, double nu[eNLIQ][19])
 {
     std::memset(nu, 0, sizeof(double) * eNLIQ * 19);
-    nu[eXxc][0] = -1; nu[eSI][0] = p.f_sI_xc; nu[eXch][0] = p.f_ch_xc;
-    nu[eXpr][0] = p.f_pr_xc; nu[eXli][0] = p.f_li_xc; nu[eXI][0] = p.f_xI_xc;
-    nu[eXch][1] = -1; nu[eSsu][1] = 1;
-    nu[eXpr][2] = -1; nu[eSaa][2] = 1;
-    nu[eXli][3] = -1; nu[eSsu][3] = 1 - p.f_fa_li; nu[eSfa][3] = p.f_fa_li;
-    nu[eSsu][4] = -1; nu[eSbu][4] = (1 - p.Y_su) * p.f_bu_su;
-    nu[eSpro][4] = (1 - p.Y_su) * p.f_pro_su; nu[eSac][4] = (1 - p.Y_su) * p.f_ac_su;
-    nu[eSh2][4] = (1 - p.Y_su) * p.f_h2_su; nu[eXsu][4] = p.Y_su;
-    nu[eSaa][5] = -1; nu[eSva][5] = (1 - p.Y_aa) * p.f_va_aa;
-    nu[eSbu][5] = (1 - p.Y_aa) * p.f_bu_aa; nu[eSpro][5] = (1 - p.Y_aa) * p.f_pro_aa;
-    nu[eSac][5] = (1 - p.Y_aa) * p.f_ac_aa; nu[eSh2][5] = (1 - p.Y_aa) * p.f_h2_aa;
-    nu[eXaa][5] = p.Y_aa;
-    nu[eSfa][6] = -1; nu[eSac][6] = (1 - p.Y_fa) * p.f_ac_fa;
-    nu[eSh2][6] = (1 - p.Y_fa) * p.f_h2_fa; nu[eXfa][6] = p.Y_fa;
-    nu[eSva][7] = -1; nu[eSpro][7] = (1 - p.Y_c4) * p.f_pro_va;
-    nu[eSac][7] = (1 - p.Y_c4) * p.f_ac_va; nu[eSh2][7] = (1 - p.Y_c4) * p.f_h2_va;
-    nu[eXc4][7] = p.Y_c4;
-    nu[eSbu][8] = -1; nu[eSac][8] = (1 - p.Y_c4) * p.f_ac_bu;
-    nu[eSh2][8] = (1 - p.Y_c4) * p.f_h2_bu; nu[eXc4][8] = p.Y_c4;
-    nu[eSpro][9] = -1; nu[eSac][9] = (1 - p.Y_pro) * p.f_ac_pro;
-    nu[eSh2][9] = (1 - p.Y_pro) * p.f_h2_pro; nu[eXpro][9] = p.Y_pro;
-    nu[eSac][10] = -1; nu[eSch4][10] = 1 - p.Y_ac; nu[eXac][10] = p.Y_ac;
-    nu[eSh2][11] = -1; nu[eSch4][11] = 1 - p.Y_h2; nu[eXh2][11] = p.Y_h2;
-    for (int b = 0; b < 7; ++b) { nu[eXsu + b][12 + b] = -1; nu[eXxc][12 + b] = 1; }
+    ADM1_PETERSEN_FILL(p, nu);
 }
 
 int derive(const adm1_params& p, DevParams& d)
@@ -169,11 +150,7 @@ int derive(const adm1_params& p, DevParams& d)
     }
     // carbon and nitrogen contents; closures
     double C[eNLIQ] = {0}, N[eNLIQ] = {0};
-    C[eSsu] = p.C_su; C[eSaa] = p.C_aa; C[eSfa] = p.C_fa; C[eSva] = p.C_va; C[eSbu] = p.C_bu;
-    C[eSpro] = p.C_pro; C[eSac] = p.C_ac; C[eSch4] = p.C_ch4; C[eSI] = p.C_sI;
-    C[eXxc] = p.C_xc; C[eXch] = p.C_ch; C[eXpr] = p.C_pr; C[eXli] = p.C_li; C[eXI] = p.C_xI;
-    N[eSaa] = p.N_aa; N[eSI] = p.N_I; N[eXxc] = p.N_xc; N[eXpr] = p.N_aa; N[eXI] = p.N_I;
-    for (int b = eXsu; b <= eXh2; ++b) { C[b] = p.C_bac; N[b] = p.N_bac; }
+    ADM1_CONTENTS(p, C, N);
     for (int j = 0; j < 19; ++j) {
         double sc = 0.0, sn = 0.0;
         for (int i = 0; i < eNLIQ; ++i) { sc += C[i] * nu[i][j]; sn += N[i] * nu[i][j]; }
@@ -208,19 +185,7 @@ int derive(const adm1_params& p, DevParams& d)
     d.P_atm = p.P_atm;
     d.inv_P_atm = 1.0 / p.P_atm;
     d.inv_K_I_nh3 = 1.0 / p.K_I_nh3;
-    d.f_sI_xc = p.f_sI_xc; d.f_xI_xc = p.f_xI_xc; d.f_ch_xc = p.f_ch_xc;
-    d.f_pr_xc = p.f_pr_xc; d.f_li_xc = p.f_li_xc; d.f_fa_li = p.f_fa_li;
-    d.nu5_bu = nu[eSbu][4]; d.nu5_pro = nu[eSpro][4]; d.nu5_ac = nu[eSac][4];
-    d.nu5_h2 = nu[eSh2][4]; d.Y_su = p.Y_su;
-    d.nu6_va = nu[eSva][5]; d.nu6_bu = nu[eSbu][5]; d.nu6_pro = nu[eSpro][5];
-    d.nu6_ac = nu[eSac][5]; d.nu6_h2 = nu[eSh2][5]; d.Y_aa = p.Y_aa;
-    d.nu7_ac = nu[eSac][6]; d.nu7_h2 = nu[eSh2][6]; d.Y_fa = p.Y_fa;
-    d.nu8_pro = nu[eSpro][7]; d.nu8_ac = nu[eSac][7]; d.nu8_h2 = nu[eSh2][7];
-    d.Y_c4 = p.Y_c4;
-    d.nu9_ac = nu[eSac][8]; d.nu9_h2 = nu[eSh2][8];
-    d.nu10_ac = nu[eSac][9]; d.nu10_h2 = nu[eSh2][9]; d.Y_pro = p.Y_pro;
-    d.nu11_ch4 = nu[eSch4][10]; d.Y_ac = p.Y_ac;
-    d.nu12_ch4 = nu[eSch4][11]; d.Y_h2 = p.Y_h2;
+    ADM1_NU_VALUES(nu, d);
     return ADM1_OK;
 }
 
@@ -301,6 +266,8 @@ using namespace adm1_abi;
 extern "C" {
 
 const char* adm1_param_names(void) { return kParamNames; }
+
+const char* adm1_model_name(void) { return ADM1_MODEL_NAME; }
 
 const char* adm1_strerror(int code)
 {

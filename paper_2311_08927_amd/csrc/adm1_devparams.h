@@ -3,14 +3,17 @@
 // Built once on the host by adm1_init from the named parameters (the
 // standard ADM1 set; section 2.2) and passed to every kernel by value, so it
 // lives in the kernel-argument segment and is read through scalar loads.
-// Stoichiometric coefficients are pre-multiplied (e.g. (1 - Y_su) f_bu_su);
-// the inorganic-carbon and -nitrogen rows of the Petersen matrix are the
-// closures nuIC_j = -sum_i C_i nu_ij and nuIN_j = -sum_i N_i nu_ij.
+// Stoichiometric coefficients are evaluated on the host from the model
+// description's expressions (e.g. (1 - Y_su) f_bu_su); the inorganic-carbon
+// and -nitrogen rows of the Petersen matrix are the closures
+// nuIC_j = -sum_i C_i nu_ij and nuIN_j = -sum_i N_i nu_ij.
 #pragma once
 
 #ifdef __cplusplus
 namespace adm1 {
 #endif
+
+#define ADM1_NU_MAX 64  // room for the coefficient table of a model description
 
 typedef struct DevParams {
     // kinetic constants at T_ref_kin (1/d, kg COD/m3, kmol/m3)
@@ -35,16 +38,10 @@ typedef struct DevParams {
     // gas phase: transfer, headspace, valve
     double kLa, kp, inv_vg, P_atm;
     double inv_P_atm, inv_K_I_nh3;
-    // stoichiometry
-    double f_sI_xc, f_xI_xc, f_ch_xc, f_pr_xc, f_li_xc, f_fa_li;
-    double nu5_bu, nu5_pro, nu5_ac, nu5_h2, Y_su;
-    double nu6_va, nu6_bu, nu6_pro, nu6_ac, nu6_h2, Y_aa;
-    double nu7_ac, nu7_h2, Y_fa;
-    double nu8_pro, nu8_ac, nu8_h2, Y_c4;
-    double nu9_ac, nu9_h2;
-    double nu10_ac, nu10_h2, Y_pro;
-    double nu11_ch4, Y_ac;
-    double nu12_ch4, Y_h2;
+    // stoichiometry: the Petersen-matrix coefficients that are not +-1, in
+    // the order of the generated table (adm1_stoich.inc, from the model
+    // description), and the inorganic carbon / nitrogen closure rows
+    double nu_v[ADM1_NU_MAX];
     double nuIC[19], nuIN[19];
     // integration control
     double rtol;

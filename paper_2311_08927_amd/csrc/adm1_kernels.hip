@@ -70,7 +70,7 @@ __device__ static void build_dense(const DevParams& p, const Partials& d, double
                                    double D, double* M)
 {
     for (int k = 0; k < NB * NB; ++k) M[k] = 0.0;
-#include "adm1_jac_dense.inc"
+#include <adm1_jac_dense.inc>
 }
 
 __device__ __forceinline__ double rms_scaled(const DevParams& p, const double* v,
@@ -123,7 +123,7 @@ struct LinDense {  // dense LU with partial pivoting (in scratch memory)
     __device__ void solve(double* b) const { lu_dense_solve(M, piv, b); }
 };
 
-#include "adm1_jac_sparse1.inc"
+#include <adm1_jac_sparse1.inc>
 
 struct LinSparse1 {  // generated static-order sparse LU, named scalars
     ADM1_SP_DECL
@@ -137,7 +137,7 @@ struct LinSparse1 {  // generated static-order sparse LU, named scalars
     __device__ void solve(double* b) const { ADM1_SP_SOLVE(b); }
 };
 
-#include "adm1_jac_sparse1_lds.inc"
+#include <adm1_jac_sparse1_lds.inc>
 
 // The LDS of the one-lane kernel with the matrix in LDS: ADM1_SPL_NNZ
 // entries of each of the 64 particles of the workgroup (124 KB; one

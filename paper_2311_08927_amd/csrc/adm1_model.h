@@ -34,7 +34,8 @@ __host__ __device__ constexpr int state_row(int k)
     return k < 7 ? k : (k < 25 ? k + 1 : k + 7);
 }
 
-#include "adm1_partials.inc"
+#include <adm1_partials.inc>
+#include <adm1_stoich.inc>
 
 // Reciprocal of a finite non-zero x: the hardware estimate refined by two
 // Newton-Raphson steps (the error squares at each step, so the estimate's
@@ -263,11 +264,7 @@ __device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const
 
     // eq. 8 (FP64) with the rate factors above
     H2Terms t;
-    t.base = inflow(ROW_SH2) + p.nu5_h2 * (double)rho[4] + p.nu6_h2 * (double)rho[5];
-    t.c7 = p.nu7_h2 * (double)b7;
-    t.c8 = p.nu8_h2 * (double)b8 + p.nu9_h2 * (double)b9;
-    t.c10 = p.nu10_h2 * (double)b10;
-    t.c12 = (double)b12;
+    ADM1_H2_TERMS(t, inflow(ROW_SH2), rho, b7, b8, b9, b10, b12);
     t.kh = c.K_H_h2 * c.RT * y[Gh2];
     if (solve_Sh2(p, t, D, Sh2, iters)) return 1;
     if (alg_only) return 0;
@@ -293,17 +290,7 @@ __device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const
     // eq. 2 assembly
     const R Dr = (R)D;
 #define ADM1_IN(k) ((R)inflow(state_row(k)) - Dr * (R)y[k])
-    out(Ssu, (double)(ADM1_IN(Ssu) + rho[1] + (R)(1.0 - p.f_fa_li) * rho[3] - rho[4]));
-    out(Saa, (double)(ADM1_IN(Saa) + rho[2] - rho[5]));
-    out(Sfa, (double)(ADM1_IN(Sfa) + (R)p.f_fa_li * rho[3] - rho[6]));
-    out(Sva, (double)(ADM1_IN(Sva) + (R)p.nu6_va * rho[5] - rho[7]));
-    out(Sbu, (double)(ADM1_IN(Sbu) + (R)p.nu5_bu * rho[4] + (R)p.nu6_bu * rho[5] - rho[8]));
-    out(Spro, (double)(ADM1_IN(Spro) + (R)p.nu5_pro * rho[4] + (R)p.nu6_pro * rho[5] +
-                       (R)p.nu8_pro * rho[7] - rho[9]));
-    out(Sac, (double)(ADM1_IN(Sac) + (R)p.nu5_ac * rho[4] + (R)p.nu6_ac * rho[5] +
-                      (R)p.nu7_ac * rho[6] + (R)p.nu8_ac * rho[7] + (R)p.nu9_ac * rho[8] +
-                      (R)p.nu10_ac * rho[9] - rho[10]));
-    out(Sch4, (double)(ADM1_IN(Sch4) + (R)p.nu11_ch4 * rho[10] + (R)p.nu12_ch4 * rho[11] - T9));
+    ADM1_ASSEMBLE_LIQUID(out, ADM1_IN, rho, R, T9, T10);
     {
         R sic = ADM1_IN(SIC) - T10, sin_ = ADM1_IN(SIN);
 #pragma unroll
@@ -314,22 +301,6 @@ __device__ __forceinline__ int rhs_in(const DevParams& p, const TConst& c, const
         out(SIC, (double)sic);
         out(SIN, (double)sin_);
     }
-    out(SI, (double)(ADM1_IN(SI) + (R)p.f_sI_xc * rho[0]));
-    out(Xxc, (double)(ADM1_IN(Xxc) - rho[0] + rho[12] + rho[13] + rho[14] + rho[15] + rho[16] +
-                      rho[17] + rho[18]));
-    out(Xch, (double)(ADM1_IN(Xch) + (R)p.f_ch_xc * rho[0] - rho[1]));
-    out(Xpr, (double)(ADM1_IN(Xpr) + (R)p.f_pr_xc * rho[0] - rho[2]));
-    out(Xli, (double)(ADM1_IN(Xli) + (R)p.f_li_xc * rho[0] - rho[3]));
-    out(Xsu, (double)(ADM1_IN(Xsu) + (R)p.Y_su * rho[4] - rho[12]));
-    out(Xaa, (double)(ADM1_IN(Xaa) + (R)p.Y_aa * rho[5] - rho[13]));
-    out(Xfa, (double)(ADM1_IN(Xfa) + (R)p.Y_fa * rho[6] - rho[14]));
-    out(Xc4, (double)(ADM1_IN(Xc4) + (R)p.Y_c4 * (rho[7] + rho[8]) - rho[15]));
-    out(Xpro, (double)(ADM1_IN(Xpro) + (R)p.Y_pro * rho[9] - rho[16]));
-    out(Xac, (double)(ADM1_IN(Xac) + (R)p.Y_ac * rho[10] - rho[17]));
-    out(Xh2, (double)(ADM1_IN(Xh2) + (R)p.Y_h2 * rho[11] - rho[18]));
-    out(XI, (double)(ADM1_IN(XI) + (R)p.f_xI_xc * rho[0]));
-    out(Scat, (double)ADM1_IN(Scat));
-    out(San, (double)ADM1_IN(San));
 #undef ADM1_IN
     const R ivg = (R)p.inv_vg;
     out(Gh2, (double)((T8 - q * (R)y[Gh2]) * ivg));

@@ -31,7 +31,7 @@
 #include "adm1_kernels.h"
 #include "adm1_model.h"
 #include "adm1_rodas4.h"
-#include "adm1_jac_sparse2.inc"
+#include <adm1_jac_sparse2.inc>
 
 namespace adm1 {
 

@@ -22,7 +22,11 @@ structure and emits:
                          static-order sparse LU, with rows split over a lane
                          pair (see emit_sparse2).
 
-Run: python gen_jac.py   (writes the .inc files next to this script)
+The Petersen matrix (stoichiometry and rate forms) is read from a model
+description, data/adm1_petersen.json by default (see load_model).
+
+Run: python gen_jac.py [--model JSON] [--out DIR]   (writes the .inc files
+next to this script, or into DIR)
 """
 from __future__ import annotations
 
@@ -61,41 +65,227 @@ RATES = {
 PROCS = ["dis", "hch", "hpr", "hli", "su", "aa", "fa", "va", "bu", "pro", "ac", "h2", "dsu",
          "daa", "dfa", "dc4", "dpro", "dac", "dh2"]
 
-# Petersen matrix: liquid row -> [(coefficient C expression, rate)]
-NU = {
-    "Ssu": [("1.0", "hch"), ("(1.0 - p.f_fa_li)", "hli"), ("-1.0", "su")],
-    "Saa": [("1.0", "hpr"), ("-1.0", "aa")],
-    "Sfa": [("p.f_fa_li", "hli"), ("-1.0", "fa")],
-    "Sva": [("p.nu6_va", "aa"), ("-1.0", "va")],
-    "Sbu": [("p.nu5_bu", "su"), ("p.nu6_bu", "aa"), ("-1.0", "bu")],
-    "Spro": [("p.nu5_pro", "su"), ("p.nu6_pro", "aa"), ("p.nu8_pro", "va"), ("-1.0", "pro")],
-    "Sac": [("p.nu5_ac", "su"), ("p.nu6_ac", "aa"), ("p.nu7_ac", "fa"), ("p.nu8_ac", "va"),
-            ("p.nu9_ac", "bu"), ("p.nu10_ac", "pro"), ("-1.0", "ac")],
-    "Sch4": [("p.nu11_ch4", "ac"), ("p.nu12_ch4", "h2"), ("-1.0", "T9")],
-    "SIC": [(f"p.nuIC[{j}]", r) for j, r in enumerate(PROCS)] + [("-1.0", "T10")],
-    "SIN": [(f"p.nuIN[{j}]", r) for j, r in enumerate(PROCS)],
-    "SI": [("p.f_sI_xc", "dis")],
-    "Xxc": [("-1.0", "dis")] + [("1.0", r) for r in PROCS[12:]],
-    "Xch": [("p.f_ch_xc", "dis"), ("-1.0", "hch")],
-    "Xpr": [("p.f_pr_xc", "dis"), ("-1.0", "hpr")],
-    "Xli": [("p.f_li_xc", "dis"), ("-1.0", "hli")],
-    "Xsu": [("p.Y_su", "su"), ("-1.0", "dsu")],
-    "Xaa": [("p.Y_aa", "aa"), ("-1.0", "daa")],
-    "Xfa": [("p.Y_fa", "fa"), ("-1.0", "dfa")],
-    "Xc4": [("p.Y_c4", "va"), ("p.Y_c4", "bu"), ("-1.0", "dc4")],
-    "Xpro": [("p.Y_pro", "pro"), ("-1.0", "dpro")],
-    "Xac": [("p.Y_ac", "ac"), ("-1.0", "dac")],
-    "Xh2": [("p.Y_h2", "h2"), ("-1.0", "dh2")],
-    "XI": [("p.f_xI_xc", "dis")],
-    "Scat": [], "San": [],
-    # gas rows: f_G = inv_vg (-q G + T)
-    "Gh2": [("-p.inv_vg", "QGh2"), ("p.inv_vg", "T8")],
-    "Gch4": [("-p.inv_vg", "QGch4"), ("p.inv_vg", "T9")],
-    "Gco2": [("-p.inv_vg", "QGco2"), ("p.inv_vg", "T10")],
+# ---------------------------------------------------------------------------
+# The Petersen matrix comes from a model description (data/adm1_petersen.json
+# by default): per process its rate form and its stoichiometric coefficients
+# as expressions of the named parameters.  The rate forms must be the ones the
+# kernel implements (KERNEL_RATES); the stoichiometry is free (any pattern
+# that conserves COD): it sets the generated eq.-2 assembly, the eq.-8
+# coefficients, the host-side derivation of the coefficients and the pattern
+# of the Newton matrix.
+# ---------------------------------------------------------------------------
+DATA = os.path.join(os.path.dirname(HERE), "data")
+DEFAULT_MODEL = os.path.join(DATA, "adm1_petersen.json")
+# 35-entry state names and the kernel's names of the 28 integrated entries
+STATE = ["S_su", "S_aa", "S_fa", "S_va", "S_bu", "S_pro", "S_ac", "S_h2", "S_ch4", "S_IC",
+         "S_IN", "S_I", "X_xc", "X_ch", "X_pr", "X_li", "X_su", "X_aa", "X_fa", "X_c4",
+         "X_pro", "X_ac", "X_h2", "X_I", "S_cat", "S_an"]
+KNAME = {s: s.replace("_", "") for s in STATE}  # S_su -> Ssu (enum YIdx / gen names)
+KNAME["S_h2"] = "Sh2"
+_fo = lambda k, s: {"form": "first_order", "k": k, "state": s}  # noqa: E731
+
+
+def _monod(k, K, S, X, f, comp=None):
+    d = {"form": "monod" if comp is None else "monod_competing", "k": k, "K": K,
+         "substrate": S, "biomass": X, "factors": f}
+    if comp is not None:
+        d["competitor"] = comp
+    return d
+
+
+KERNEL_RATES = {
+    "dis": _fo("k_dis", "X_xc"), "hch": _fo("k_hyd_ch", "X_ch"),
+    "hpr": _fo("k_hyd_pr", "X_pr"), "hli": _fo("k_hyd_li", "X_li"),
+    "su": _monod("k_m_su", "K_S_su", "S_su", "X_su", ["I_pH_aa", "I_IN_lim"]),
+    "aa": _monod("k_m_aa", "K_S_aa", "S_aa", "X_aa", ["I_pH_aa", "I_IN_lim"]),
+    "fa": _monod("k_m_fa", "K_S_fa", "S_fa", "X_fa", ["I_pH_aa", "I_IN_lim", "I_h2_fa"]),
+    "va": _monod("k_m_c4", "K_S_c4", "S_va", "X_c4", ["I_pH_aa", "I_IN_lim", "I_h2_c4"],
+                 "S_bu"),
+    "bu": _monod("k_m_c4", "K_S_c4", "S_bu", "X_c4", ["I_pH_aa", "I_IN_lim", "I_h2_c4"],
+                 "S_va"),
+    "pro": _monod("k_m_pro", "K_S_pro", "S_pro", "X_pro", ["I_pH_aa", "I_IN_lim",
+                                                          "I_h2_pro"]),
+    "ac": _monod("k_m_ac", "K_S_ac", "S_ac", "X_ac", ["I_pH_ac", "I_IN_lim", "I_nh3"]),
+    "h2": _monod("k_m_h2", "K_S_h2", "S_h2", "X_h2", ["I_pH_h2", "I_IN_lim"]),
+    "dsu": _fo("k_dec_su", "X_su"), "daa": _fo("k_dec_aa", "X_aa"),
+    "dfa": _fo("k_dec_fa", "X_fa"), "dc4": _fo("k_dec_c4", "X_c4"),
+    "dpro": _fo("k_dec_pro", "X_pro"), "dac": _fo("k_dec_ac", "X_ac"),
+    "dh2": _fo("k_dec_h2", "X_h2"),
 }
-# eq. 8 residual E8 = D (S_h2,in - S_h2) + sum_j nu_h2,j rho_j - T8
-NU_H2 = [("p.nu5_h2", "su"), ("p.nu6_h2", "aa"), ("p.nu7_h2", "fa"), ("p.nu8_h2", "va"),
-         ("p.nu9_h2", "bu"), ("p.nu10_h2", "pro"), ("-1.0", "h2"), ("-1.0", "T8")]
+# processes whose rate depends on S_h2 and the eq.-8 coefficient they feed
+H2_DEPENDENT = {"fa": "c7", "va": "c8", "bu": "c8", "pro": "c10", "h2": "c12"}
+TRANSFER_ROWS = {"S_h2": "T8", "S_ch4": "T9", "S_IC": "T10"}
+
+
+def c_expr(text: str, names: set) -> str:
+    """A coefficient expression of the description (numbers, parameter names,
+    + - * / and parentheses) as C on the adm1_params struct p."""
+    import ast
+
+    def emit(n):
+        if isinstance(n, ast.Expression):
+            return emit(n.body)
+        if isinstance(n, ast.BinOp) and type(n.op) in (ast.Add, ast.Sub, ast.Mult, ast.Div):
+            op = {ast.Add: "+", ast.Sub: "-", ast.Mult: "*", ast.Div: "/"}[type(n.op)]
+            return f"({emit(n.left)} {op} {emit(n.right)})"
+        if isinstance(n, ast.UnaryOp) and isinstance(n.op, (ast.USub, ast.UAdd)):
+            return f"({'-' if isinstance(n.op, ast.USub) else '+'}{emit(n.operand)})"
+        if isinstance(n, ast.Constant) and isinstance(n.value, (int, float)):
+            return repr(float(n.value))
+        if isinstance(n, ast.Name):
+            if n.id not in names:
+                raise ValueError(f"unknown parameter {n.id!r} in {text!r}")
+            return f"p.{n.id}"
+        raise ValueError(f"unsupported expression {text!r}")
+    return emit(ast.parse(text, mode="eval"))
+
+
+def param_names() -> set:
+    import json
+    with open(os.path.join(DATA, "adm1_params.json")) as fh:
+        return set(json.load(fh)["values"])
+
+
+def load_model(path: str = DEFAULT_MODEL) -> dict:
+    """Read and check a model description; returns it with, per process, the
+    stoichiometry as {state: (C expression, unit coefficient or None)}."""
+    import json
+    with open(path) as fh:
+        m = json.load(fh)
+    names = param_names()
+    procs = m["processes"]
+    if [q["name"] for q in procs] != PROCS:
+        raise ValueError(f"{path}: the processes must be {PROCS} in that order")
+    for q in procs:
+        if q["rate"] != KERNEL_RATES[q["name"]]:
+            raise ValueError(f"{path}: rate form of {q['name']!r} is not the kernel's "
+                             f"{KERNEL_RATES[q['name']]}")
+        for st in q["stoich"]:
+            if st not in STATE or st in m["closures"]:
+                raise ValueError(f"{path}: process {q['name']!r} sets {st!r}, which is not "
+                                 "an organic liquid entry")
+        q["c"] = {}
+        for st, e in q["stoich"].items():
+            t = e.replace(" ", "")
+            unit = 1.0 if t == "1" else (-1.0 if t == "-1" else None)
+            q["c"][st] = (c_expr(e, names), unit)
+    if m["closures"] != {"S_IC": "carbon", "S_IN": "nitrogen"}:
+        raise ValueError(f"{path}: the closures must be S_IC (carbon) and S_IN (nitrogen)")
+    if m.get("transfers") != TRANSFER_ROWS:
+        raise ValueError(f"{path}: the liquid-gas transfers must be {TRANSFER_ROWS}")
+    for kind in ("carbon", "nitrogen"):
+        m["contents"][kind] = {st: c_expr(e, names) for st, e in m["contents"][kind].items()}
+    # table of the distinct coefficients that are not +-1, in process order of
+    # their first use (a coefficient shared by several processes is one slot)
+    m["table"], m["slot"], first = [], {}, {}
+    for j, q in enumerate(procs):
+        for st, (e, u) in q["c"].items():
+            if u is not None:
+                continue
+            if e not in first:
+                first[e] = len(m["table"])
+                m["table"].append((j, st))
+            m["slot"][(j, st)] = first[e]
+    return m
+
+
+MODEL = None
+
+
+def use_model(path: str = DEFAULT_MODEL):
+    """Set the Petersen matrix NU (liquid row -> [(coefficient, rate)]) and the
+    eq.-8 row NU_H2 from a description."""
+    global MODEL, NU, NU_H2
+    MODEL = load_model(path)
+    NU = {KNAME[st]: [] for st in STATE if st not in ("S_h2",)}
+    NU_H2 = []
+    for j, q in enumerate(MODEL["processes"]):
+        for st, (e, u) in q["c"].items():
+            coef = ("1.0" if u == 1.0 else "-1.0") if u is not None else \
+                f"p.nu_v[{MODEL['slot'][(j, st)]}]"
+            if st == "S_h2":
+                NU_H2.append((coef, q["name"]))
+            else:
+                NU[KNAME[st]].append((coef, q["name"]))
+    NU["SIC"] = [(f"p.nuIC[{j}]", r) for j, r in enumerate(PROCS)] + [("-1.0", "T10")]
+    NU["SIN"] = [(f"p.nuIN[{j}]", r) for j, r in enumerate(PROCS)]
+    NU["Sch4"].append(("-1.0", "T9"))
+    NU_H2.append(("-1.0", "T8"))
+    # gas rows: f_G = inv_vg (-q G + T)
+    NU["Gh2"] = [("-p.inv_vg", "QGh2"), ("p.inv_vg", "T8")]
+    NU["Gch4"] = [("-p.inv_vg", "QGch4"), ("p.inv_vg", "T9")]
+    NU["Gco2"] = [("-p.inv_vg", "QGco2"), ("p.inv_vg", "T10")]
+
+
+def emit_stoich() -> str:
+    """Host code of the coefficients (ADM1_PETERSEN_FILL: the organic rows of
+    the Petersen matrix from the named parameters; ADM1_NU_VALUES: the table
+    of the coefficients that are not +-1, as the kernels read it;
+    ADM1_CONTENTS: carbon and nitrogen contents) and the device code of the
+    eq.-2 assembly of the liquid rows and of the eq.-8 coefficients."""
+    m = MODEL
+    procs = m["processes"]
+    e = lambda st: "e" + KNAME[st].replace("Sh2", "Sh2")  # noqa: E731
+    out = [f"// Generated by gen_jac.py from the model description {m['model']!r}.",
+           "#pragma once",
+           f"#define ADM1_MODEL_NAME \"{m['model']}\"",
+           f"#define ADM1_NU_COUNT {len(m['table'])}",
+           "#define ADM1_PETERSEN_FILL(p, nu) \\"]
+    for j, q in enumerate(procs):
+        for st, (ex, u) in q["c"].items():
+            out.append(f"    nu[{e(st)}][{j}] = {repr(u) if u is not None else ex}; \\")
+    out.append("    (void)0")
+    out.append("#define ADM1_NU_VALUES(nu, d) \\")
+    for k, (j, st) in enumerate(m["table"]):
+        out.append(f"    d.nu_v[{k}] = nu[{e(st)}][{j}]; \\")
+    out.append("    (void)0")
+    out.append("#define ADM1_CONTENTS(p, C, N) \\")
+    for st, ex in m["contents"]["carbon"].items():
+        out.append(f"    C[{e(st)}] = {ex}; \\")
+    for st, ex in m["contents"]["nitrogen"].items():
+        out.append(f"    N[{e(st)}] = {ex}; \\")
+    out.append("    (void)0")
+    # device: eq.-2 assembly of the organic liquid rows (rates rho[19], the
+    # inflow term IN(k), transfers T9 / T10 in their rows)
+    out.append("#define ADM1_ASSEMBLE_LIQUID(out, IN, rho, R, T9, T10) \\")
+    for st in STATE:
+        if st in ("S_h2", "S_IC", "S_IN"):
+            continue
+        k = KNAME[st]
+        terms = []
+        for j, q in enumerate(procs):
+            if st in q["c"]:
+                ex, u = q["c"][st]
+                if u == 1.0:
+                    terms.append(f" + rho[{j}]")
+                elif u == -1.0:
+                    terms.append(f" - rho[{j}]")
+                else:
+                    terms.append(f" + (R)p.nu_v[{m['slot'][(j, st)]}] * rho[{j}]")
+        if st == "S_ch4":
+            terms.append(" - T9")
+        out.append(f"    out({k}, (double)(IN({k}){''.join(terms)})); \\")
+    out.append("    (void)0")
+    # device: eq.-8 coefficients from the S_h2 row
+    base, groups = [], {"c7": [], "c8": [], "c10": [], "c12": []}
+    rate_of = {"fa": "b7", "va": "b8", "bu": "b9", "pro": "b10", "h2": "b12"}
+    for j, q in enumerate(procs):
+        if "S_h2" not in q["c"]:
+            continue
+        ex, u = q["c"]["S_h2"]
+        coef = repr(u) if u is not None else f"p.nu_v[{m['slot'][(j, 'S_h2')]}]"
+        if q["name"] in H2_DEPENDENT:
+            g = H2_DEPENDENT[q["name"]]
+            sign = "-" if g == "c12" else ""
+            groups[g].append(f"{sign}({coef}) * (double){rate_of[q['name']]}")
+        else:
+            base.append(f" + ({coef}) * (double)rho[{j}]")
+    out.append("#define ADM1_H2_TERMS(t, h2in, rho, b7, b8, b9, b10, b12) \\")
+    out.append(f"    t.base = h2in{''.join(base)}; \\")
+    for g, terms in groups.items():
+        out.append(f"    t.{g} = {' + '.join(terms) if terms else '0.0'}; \\")
+    out.append("    (void)0")
+    return "\n".join(out) + "\n"
 
 
 def partial_names():
@@ -513,25 +703,36 @@ def emit_sparse2():
 
 
 def main():
-    with open(os.path.join(HERE, "adm1_jac_sparse2.inc"), "w") as fh:
+    import argparse
+    import json
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--model", default=DEFAULT_MODEL, help="model description (JSON)")
+    ap.add_argument("--out", default=HERE, help="directory of the generated files")
+    ap.add_argument("--stats", action="store_true")
+    args = ap.parse_args()
+    use_model(args.model)
+    out = lambda name: os.path.join(args.out, name)  # noqa: E731
+    with open(out("adm1_stoich.inc"), "w") as fh:
+        fh.write(emit_stoich())
+    with open(out("adm1_jac_sparse2.inc"), "w") as fh:
         txt, counts, nslots = emit_sparse2()
         fh.write(txt)
-    if "--stats" in sys.argv:
+    if args.stats:
         print("sparse2 slots/lane", nslots, counts)
-    with open(os.path.join(HERE, "adm1_partials.inc"), "w") as fh:
+    with open(out("adm1_partials.inc"), "w") as fh:
         fh.write("// Generated by gen_jac.py -- do not edit.\n" + emit_partials_struct() + "\n")
-    with open(os.path.join(HERE, "adm1_jac_dense.inc"), "w") as fh:
+    with open(out("adm1_jac_dense.inc"), "w") as fh:
         fh.write(emit_dense())
-    with open(os.path.join(HERE, "adm1_jac_sparse1.inc"), "w") as fh:
+    with open(out("adm1_jac_sparse1.inc"), "w") as fh:
         fh.write(emit_sparse1())
-    with open(os.path.join(HERE, "adm1_jac_sparse1_lds.inc"), "w") as fh:
+    with open(out("adm1_jac_sparse1_lds.inc"), "w") as fh:
         fh.write(emit_sparse1_lds())
     stats = lu_counts()
     stats["assembly_flops"] = assembly_flops()
-    import json
-    with open(os.path.join(HERE, "adm1_lu_stats.json"), "w") as fh:
+    stats["model"] = MODEL["model"]
+    with open(out("adm1_lu_stats.json"), "w") as fh:
         json.dump(stats, fh, indent=1)
-    if "--stats" in sys.argv:
+    if args.stats:
         print(json.dumps({k: v for k, v in stats.items() if k != "order"}))
         print("order:", " ".join(stats["order"]))
 

@@ -105,6 +105,10 @@ def default_floor() -> np.ndarray:
 # C-named entry points
 # ---------------------------------------------------------------------------
 def adm1_surrogate_create(ctx: int, n_max: int, batch_max: int) -> int:
+    if A.model_name(ctx) != "adm1":
+        # features, targets and the fallback belong to the standard matrix
+        raise ValueError(f"the surrogate models the standard ADM1 matrix, not "
+                         f"{A.model_name(ctx)!r}")
     h = ctypes.c_void_p()
     _check(_lib().adm1_surrogate_create(ctx, int(n_max), int(batch_max), ctypes.byref(h)),
            "adm1_surrogate_create")

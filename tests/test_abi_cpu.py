@@ -34,10 +34,14 @@ def test_header_declares_the_boundary():
         assert f in fns
 
 
-def test_library_exports_every_declared_symbol():
-    lib = A.lib()
+@pytest.mark.parametrize("model", [None, "adm1_decay_to_particulates"])
+def test_library_exports_every_declared_symbol(model):
+    """Each model description's library exports the whole boundary and
+    reports the description it was generated from."""
+    lib = A.lib(model)
     for f in declared_functions():
         assert hasattr(lib, f), f
+    assert lib.adm1_model_name().decode() == (model or "adm1")
 
 
 def test_param_names_match_header_and_data():
@@ -76,7 +80,9 @@ def test_ctypes_layout_matches_c(tmp_path):
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
-    monkeypatch.setattr(A, "_lib", None)
+    monkeypatch.setattr(A, "_libs", {})
     monkeypatch.setattr(A, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="not built"):
         A.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        A.lib("adm1_no_such_model")
