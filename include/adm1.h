@@ -136,16 +136,26 @@ enum {
     ADM1_VARIANT_COUNT = 4
 };
 
-/* Feed description (device pointers).  D[i]: dilution rate q/V of particle i
- * (1/d, 0 = closed particle); idx[i]: row of S_in giving its inflow
- * concentrations; S_in: float64 [n_feed][26], inflow of state entries 0..25
- * (entry 7 is the S_h2 inflow of eq. 8). */
+/* Per-particle inputs of the open-reactor balance (device pointers).  D[i]:
+ * dilution rate q/V of particle i (1/d, 0 = closed particle); idx[i]: row of
+ * S_in giving its inflow concentrations; S_in: float64 [n_feed][26], inflow
+ * of state entries 0..25 (entry 7 is the S_h2 inflow of eq. 8).
+ * phase (nullable): uint8 phase id of each particle (sec. 5, particles of
+ * several kinds such as sediments or inert matter).  A phase scales every
+ * biochemical rate of eq. 2 of its particles by the phase's kinetic factor
+ * (adm1_set_phase_kinetics; 0 = inert, reactions off); dilution and the
+ * liquid-gas transfers act in every phase.  NULL: every particle has
+ * factor 1. */
 typedef struct adm1_feed {
     const double *D;
     const int32_t *idx;
     const double *S_in;
     int64_t n_feed;
+    const uint8_t *phase;
 } adm1_feed;
+
+/* Number of phase ids (the uint8 range). */
+#define ADM1_MAX_PHASES 256
 
 /* Warm starts carried from one coupling interval to the next (device
  * pointers, length >= n): H[i] = S_H+ (kmol/m3), h_last[i] = the step size
@@ -544,7 +554,9 @@ int adm1_surrogate_gate(adm1_surrogate *s, double *state, int64_t ld, const doub
  * the exact step (ADM1_VARIANT_SPARSE2 kernel) on the rejected particles
  * from their pre-step states.  Arguments as in adm1_step_particles and
  * adm1_surrogate_gate; fb_count (nullable, device int32) receives the number
- * of rejected particles.  n <= the surrogate's n_max. */
+ * of rejected particles.  n <= the surrogate's n_max.  The surrogate models
+ * one phase: a feed with a phase array is ADM1_E_FEED here and in
+ * adm1_surrogate_gate and adm1_surrogate_graph_capture_step. */
 int adm1_surrogate_step(adm1_surrogate *s, double *state, int64_t ld, const double *temp_K,
                         const adm1_feed *feed, double dt_days, int64_t n,
                         const adm1_gate *gate, adm1_aux *aux, uint8_t *status,
@@ -576,6 +588,14 @@ void adm1_surrogate_destroy(adm1_surrogate *s);
 
 /* Comma-separated adm1_params field names in struct order (static string). */
 const char *adm1_param_names(void);
+
+/* Kinetic factors of the particle phases (sec. 5, multiple phases): kin is
+ * HOST memory of n_phases (0..ADM1_MAX_PHASES) float64 factors, each finite
+ * and >= 0; phase id k < n_phases gets kin[k], every other id 1 (the
+ * factors a new context starts with).  ADM1_E_OPTS for a bad count or
+ * factor (the table is then unchanged).  Synchronous.  Not supported by the
+ * surrogate calls (a feed with phases is ADM1_E_FEED there). */
+int adm1_set_phase_kinetics(adm1_ctx *ctx, const double *kin, int32_t n_phases);
 
 /* Name of the model description this library was generated from (sec. 2.2,
  * eq. 2: the Petersen matrix as data; static string): "adm1" for the

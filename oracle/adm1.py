@@ -58,18 +58,18 @@ def lib():
         L.orc_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_int64, dp, dp,
                               ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int64,
                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                              ctypes.c_void_p, ctypes.c_int]
+                              ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
         L.orc_run_fixed.restype = ctypes.c_int
         L.orc_run_fixed.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_int64, dp,
                                     dp, ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
-                                    ctypes.c_int]
+                                    ctypes.c_int, ctypes.c_void_p]
         L.orc_rhs.restype = ctypes.c_int
         L.orc_rhs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_double,
-                              ctypes.c_double, dp, dp, dp, dp]
+                              ctypes.c_double, dp, dp, dp, dp, ctypes.c_double]
         L.orc_jacobian.restype = ctypes.c_int
         L.orc_jacobian.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_double,
-                                   ctypes.c_double, dp, dp]
+                                   ctypes.c_double, dp, dp, ctypes.c_double]
         L.orc_solve_ph.restype = ctypes.c_int
         L.orc_solve_ph.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_double,
                                    ctypes.c_double, dp]
@@ -87,7 +87,7 @@ def lib():
         L.orc_fixed.restype = ctypes.c_int
         L.orc_fixed.argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, ctypes.c_double,
                                 ctypes.c_double, dp, ctypes.c_double, ctypes.c_int,
-                                ctypes.c_int]
+                                ctypes.c_int, ctypes.c_double]
         L.orc_petersen.argtypes = [ctypes.c_void_p, dp]
         L.orc_contents.argtypes = [ctypes.c_void_p, dp, dp]
         L.orc_inhib.restype = ctypes.c_double
@@ -106,6 +106,20 @@ def _dp(a: np.ndarray):
 
 def _vp(a):
     return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def particle_kin(phase, phase_kin, n):
+    """Per-particle kinetic factors from phase ids and the factor of each id
+    (ids beyond the table: 1); None when there are no phases."""
+    if phase is None:
+        return None
+    table = np.ones(256)
+    if phase_kin is not None:
+        k = np.asarray(phase_kin, dtype=np.float64)
+        table[:k.size] = k
+    ph = np.asarray(phase)[:n]
+    assert ph.dtype == np.uint8
+    return np.ascontiguousarray(table[ph])
 
 
 class Oracle:
@@ -150,23 +164,24 @@ class Oracle:
         self.rtol, self.atol = rtol, atol
 
     # -- per-particle pieces -------------------------------------------------
-    def rhs(self, x, T, D, s_in, H_guess=-1.0):
-        """f (28, integration order), consistent 35-state, S_H+."""
+    def rhs(self, x, T, D, s_in, H_guess=-1.0, kin=1.0):
+        """f (28, integration order), consistent 35-state, S_H+; kin: the
+        kinetic factor of the particle's phase."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         s_in = np.ascontiguousarray(s_in, dtype=np.float64)
         f = np.zeros(ND); xa = np.zeros(NX); H = np.array([H_guess])
         rc = lib().orc_rhs(ctypes.byref(self._p), ctypes.byref(self._o), _dp(x), T, D,
-                           _dp(s_in), _dp(f), _dp(xa), _dp(H))
+                           _dp(s_in), _dp(f), _dp(xa), _dp(H), float(kin))
         if rc != 0:
             raise RuntimeError("algebraic solve failed")
         return f, xa, float(H[0])
 
-    def jacobian(self, x, T, D, s_in):
+    def jacobian(self, x, T, D, s_in, kin=1.0):
         x = np.ascontiguousarray(x, dtype=np.float64)
         s_in = np.ascontiguousarray(s_in, dtype=np.float64)
         J = np.zeros((ND, ND))
         rc = lib().orc_jacobian(ctypes.byref(self._p), ctypes.byref(self._o), _dp(x), T, D,
-                                _dp(s_in), _dp(J))
+                                _dp(s_in), _dp(J), float(kin))
         if rc != 0:
             raise RuntimeError("algebraic solve failed")
         return J
@@ -225,7 +240,7 @@ class Oracle:
         lib().orc_contents(ctypes.byref(self._p), _dp(C), _dp(N))
         return C, N
 
-    def fixed(self, x, T, D, s_in, dt, nsteps, method="rk4"):
+    def fixed(self, x, T, D, s_in, dt, nsteps, method="rk4", kin=1.0):
         """nsteps equal steps of `method` over dt: "rk4", "rodas4" (no step
         control) or "euler" (the explicit update of the paper's fixed-step
         scheme, sec. 2.3 and 4.3); then the algebraic write-back."""
@@ -233,13 +248,13 @@ class Oracle:
         s_in = np.ascontiguousarray(s_in, dtype=np.float64)
         code = {"rk4": 0, "rodas4": 1, "euler": 2}[method]
         rc = lib().orc_fixed(ctypes.byref(self._p), ctypes.byref(self._o), _dp(x), T, D,
-                             _dp(s_in), dt, nsteps, code)
+                             _dp(s_in), dt, nsteps, code, float(kin))
         if rc != 0:
             raise RuntimeError("fixed-step integration failed")
         return x
 
     def run_fixed(self, X, T, D, fidx, feed, dt, nsteps, method="euler", n=None,
-                  nthreads=None):
+                  nthreads=None, phase=None, phase_kin=None):
         """The fixed-step scheme (see `fixed`) over particles 0..n-1 of X[35][ld]
         in place, equal particle chunks over nthreads threads.  Returns status
         uint8[n] (1 where a particle's integration failed)."""
@@ -252,20 +267,23 @@ class Oracle:
         feed = np.ascontiguousarray(feed, dtype=np.float64)
         code = {"rk4": 0, "rodas4": 1, "euler": 2}[method]
         status = np.zeros(n, dtype=np.uint8)
+        kin = particle_kin(phase, phase_kin, n)     # referenced until the call returns
         if nthreads is None:
             nthreads = len(os.sched_getaffinity(0))
         rc = lib().orc_run_fixed(ctypes.byref(self._p), ctypes.byref(self._o), _dp(X), ld,
                                  _dp(T), _dp(D), _vp(fidx), _dp(feed), dt, int(nsteps), code,
-                                 n, _vp(status), int(nthreads))
+                                 n, _vp(status), int(nthreads), _vp(kin))
         if rc != 0:
             raise RuntimeError("oracle fixed-step run failed")
         return status
 
     # -- batched step ----------------------------------------------------------
     def step(self, X, T, D, fidx, feed, dt, H=None, hlast=None, nthreads=None,
-             n=None):
-        """Advance particles in place.  X: float64 [35][ld].  Returns
-        (status uint8[n], stats int32[3][ld]: accepted, rejected, newton)."""
+             n=None, phase=None, phase_kin=None):
+        """Advance particles in place.  X: float64 [35][ld].  phase: uint8
+        phase id per particle (None: all factor 1); phase_kin: kinetic factor
+        per id (ids beyond it: 1).  Returns (status uint8[n], stats
+        int32[3][ld]: accepted, rejected, newton)."""
         assert X.dtype == np.float64 and X.flags["C_CONTIGUOUS"] and X.shape[0] == NX
         ld = X.shape[1]
         n = ld if n is None else n
@@ -276,11 +294,12 @@ class Oracle:
         assert feed.ndim == 2 and feed.shape[1] == NLIQ
         status = np.zeros(n, dtype=np.uint8)
         stats = np.zeros((3, ld), dtype=np.int32)
+        kin = particle_kin(phase, phase_kin, n)     # referenced until the call returns
         if nthreads is None:
             nthreads = len(os.sched_getaffinity(0))
         rc = lib().orc_run(ctypes.byref(self._p), ctypes.byref(self._o), _dp(X), ld,
                            _dp(T), _dp(D), _vp(fidx), _dp(feed), dt, n, _vp(H), _vp(hlast),
-                           _vp(status), _vp(stats), int(nthreads))
+                           _vp(status), _vp(stats), int(nthreads), _vp(kin))
         if rc != 0:
             raise RuntimeError("oracle run failed")
         return status, stats

@@ -134,6 +134,21 @@ typedef struct {
     double RT, K_w, K_a_co2, K_a_IN, K_H_h2, K_H_ch4, K_H_co2, p_h2o, arr;
 } orc_tconst;
 
+static orc_tconst orc_tconsts(const orc_params *p, double T);
+
+/* Multiple phases (sec. 5: particles of several kinds, such as sediments or
+ * inert matter): a phase scales every biochemical rate of the particle by
+ * its kinetic factor kin (0: an inert phase, reactions off), while dilution
+ * and the liquid-gas transfers act as in any particle.  Every rate of eq. 2
+ * carries the temperature factor arr as a multiplier, so the phase factor
+ * is applied there. */
+static orc_tconst phase_tconsts(const orc_params *p, double T, double kin)
+{
+    orc_tconst c = orc_tconsts(p, T);
+    c.arr *= kin;
+    return c;
+}
+
 static orc_tconst orc_tconsts(const orc_params *p, double T)
 {
     orc_tconst c;
@@ -781,13 +796,14 @@ static int finite_all(const double *v, int n)
 
 /* x: 35-entry state, in place.  H_io / hlast_io: warm starts (<= 0: cold),
  * updated on success.  stats: accepted, rejected, algebraic Newton iterations.
- * A failed particle keeps its input state. */
+ * kin: the kinetic factor of the particle's phase.  A failed particle keeps
+ * its input state. */
 static int advance(const orc_params *p, const orc_opts *o, double *x, double T, double D,
                    const double *s_in, double dt, double *H_io, double *hlast_io,
-                   int *stats)
+                   int *stats, double kin)
 {
     orc_model m;
-    m.p = p; m.o = o; m.c = orc_tconsts(p, T); m.D = D;
+    m.p = p; m.o = o; m.c = phase_tconsts(p, T, kin); m.D = D;
     petersen(p, m.nu);
     for (int i = 0; i < NLIQ; i++) m.s_in[i] = s_in[i];
     m.H_guess = (H_io && *H_io > 0.0) ? *H_io : -1.0;
@@ -872,7 +888,7 @@ typedef struct {
     const orc_params *p; const orc_opts *o;
     double *X; int64_t ld; const double *T; const double *D; const int32_t *fidx;
     const double *feed; double dt; double *H; double *hl; uint8_t *status;
-    int32_t *stats; int64_t i0, i1;
+    int32_t *stats; const double *kin; int64_t i0, i1;
 } orc_job;
 
 static void *run_chunk(void *arg)
@@ -885,7 +901,8 @@ static void *run_chunk(void *arg)
         int st[3];
         double H = j->H ? j->H[i] : -1.0, hl = j->hl ? j->hl[i] : -1.0;
         const int s = advance(j->p, j->o, x, j->T[i], j->D[i],
-                              j->feed + (int64_t)j->fidx[i] * NLIQ, j->dt, &H, &hl, st);
+                              j->feed + (int64_t)j->fidx[i] * NLIQ, j->dt, &H, &hl, st,
+                              j->kin ? j->kin[i] : 1.0);
         if ((s & 0x7f) == ORC_OK) {
             scatter(j->X, j->ld, i, x);
             if (j->H) j->H[i] = H;
@@ -903,11 +920,12 @@ static void *run_chunk(void *arg)
 /* Advance particles 0..n-1 by dt.  feed: [n_feed][26] inflow concentrations,
  * fidx[i] selects particle i's row; D[i] its dilution rate (1/d); T[i] its
  * temperature (K).  H, hlast: warm starts (NULL or <= 0 entries: cold).
- * stats (nullable): [3][ld] accepted, rejected, Newton iterations. */
+ * stats (nullable): [3][ld] accepted, rejected, Newton iterations.  kin
+ * (nullable: all 1): kin[i] is the kinetic factor of particle i's phase. */
 int orc_run(const orc_params *p, const orc_opts *o, double *X, int64_t ld,
             const double *T, const double *D, const int32_t *fidx, const double *feed,
             double dt, int64_t n, double *H, double *hlast, uint8_t *status,
-            int32_t *stats, int nthreads)
+            int32_t *stats, int nthreads, const double *kin)
 {
     if (orc_check_params(p)) return -1;
     if (nthreads < 1) nthreads = 1;
@@ -919,7 +937,7 @@ int orc_run(const orc_params *p, const orc_opts *o, double *X, int64_t ld,
         orc_job *j = &jobs[t];
         j->p = p; j->o = o; j->X = X; j->ld = ld; j->T = T; j->D = D; j->fidx = fidx;
         j->feed = feed; j->dt = dt; j->H = H; j->hl = hlast; j->status = status;
-        j->stats = stats;
+        j->stats = stats; j->kin = kin;
         j->i0 = n * t / nthreads;
         j->i1 = n * (t + 1) / nthreads;
     }
@@ -934,10 +952,10 @@ int orc_run(const orc_params *p, const orc_opts *o, double *X, int64_t ld,
  * 28 derivatives in integration order, and the consistent 35-entry state
  * (algebraic entries solved) in x_alg, and S_H+ in *H.  Returns 0 / -1. */
 int orc_rhs(const orc_params *p, const orc_opts *o, const double *x, double T, double D,
-            const double *s_in, double *f, double *x_alg, double *H)
+            const double *s_in, double *f, double *x_alg, double *H, double kin)
 {
     orc_model m;
-    m.p = p; m.o = o; m.c = orc_tconsts(p, T); m.D = D;
+    m.p = p; m.o = o; m.c = phase_tconsts(p, T, kin); m.D = D;
     petersen(p, m.nu);
     for (int i = 0; i < NLIQ; i++) m.s_in[i] = s_in[i];
     m.H_guess = (H && *H > 0.0) ? *H : -1.0;
@@ -957,10 +975,10 @@ int orc_rhs(const orc_params *p, const orc_opts *o, const double *x, double T, d
 
 /* Total Jacobian df/dy, 28x28 row-major, integration order. */
 int orc_jacobian(const orc_params *p, const orc_opts *o, const double *x, double T,
-                 double D, const double *s_in, double *J)
+                 double D, const double *s_in, double *J, double kin)
 {
     orc_model m;
-    m.p = p; m.o = o; m.c = orc_tconsts(p, T); m.D = D;
+    m.p = p; m.o = o; m.c = phase_tconsts(p, T, kin); m.D = D;
     petersen(p, m.nu);
     for (int i = 0; i < NLIQ; i++) m.s_in[i] = s_in[i];
     m.H_guess = -1.0;
@@ -1059,10 +1077,10 @@ void orc_gas_flux(const orc_params *p, const double *x, double T, double V_liq,
  * internal steps), method 2.  Every evaluation of f solves eqs. 7 and 8 at
  * the current differential state.  A non-finite state after a step fails. */
 int orc_fixed(const orc_params *p, const orc_opts *o, double *x, double T, double D,
-              const double *s_in, double dt, int nsteps, int method)
+              const double *s_in, double dt, int nsteps, int method, double kin)
 {
     orc_model m;
-    m.p = p; m.o = o; m.c = orc_tconsts(p, T); m.D = D;
+    m.p = p; m.o = o; m.c = phase_tconsts(p, T, kin); m.D = D;
     petersen(p, m.nu);
     for (int i = 0; i < NLIQ; i++) m.s_in[i] = s_in[i];
     m.H_guess = -1.0;
@@ -1107,7 +1125,8 @@ int orc_fixed(const orc_params *p, const orc_opts *o, double *x, double T, doubl
 typedef struct {
     const orc_params *p; const orc_opts *o;
     double *X; int64_t ld; const double *T; const double *D; const int32_t *fidx;
-    const double *feed; double dt; int nsteps, method; uint8_t *status; int64_t i0, i1;
+    const double *feed; double dt; int nsteps, method; uint8_t *status; const double *kin;
+    int64_t i0, i1;
 } orc_fixed_job;
 
 static void *run_fixed_chunk(void *arg)
@@ -1118,7 +1137,7 @@ static void *run_fixed_chunk(void *arg)
         gather(j->X, j->ld, i, x);
         const int rc = orc_fixed(j->p, j->o, x, j->T[i], j->D[i],
                                  j->feed + (int64_t)j->fidx[i] * NLIQ, j->dt, j->nsteps,
-                                 j->method);
+                                 j->method, j->kin ? j->kin[i] : 1.0);
         if (rc == 0) scatter(j->X, j->ld, i, x);
         j->status[i] = rc == 0 ? 0 : 1;
     }
@@ -1127,7 +1146,8 @@ static void *run_fixed_chunk(void *arg)
 
 int orc_run_fixed(const orc_params *p, const orc_opts *o, double *X, int64_t ld,
                   const double *T, const double *D, const int32_t *fidx, const double *feed,
-                  double dt, int nsteps, int method, int64_t n, uint8_t *status, int nthreads)
+                  double dt, int nsteps, int method, int64_t n, uint8_t *status, int nthreads,
+                  const double *kin)
 {
     if (orc_check_params(p) || nsteps < 1) return -1;
     if (nthreads < 1) nthreads = 1;
@@ -1139,7 +1159,7 @@ int orc_run_fixed(const orc_params *p, const orc_opts *o, double *X, int64_t ld,
         orc_fixed_job *j = &jobs[t];
         j->p = p; j->o = o; j->X = X; j->ld = ld; j->T = T; j->D = D; j->fidx = fidx;
         j->feed = feed; j->dt = dt; j->nsteps = nsteps; j->method = method;
-        j->status = status;
+        j->status = status; j->kin = kin;
         j->i0 = n * t / nthreads;
         j->i1 = n * (t + 1) / nthreads;
     }

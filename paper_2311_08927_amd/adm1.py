@@ -43,7 +43,7 @@ class adm1_opts(ctypes.Structure):
 
 class adm1_feed(ctypes.Structure):
     _fields_ = [("D", ctypes.c_void_p), ("idx", ctypes.c_void_p), ("S_in", ctypes.c_void_p),
-                ("n_feed", ctypes.c_int64)]
+                ("n_feed", ctypes.c_int64), ("phase", ctypes.c_void_p)]
 
 
 class adm1_aux(ctypes.Structure):
@@ -116,6 +116,8 @@ def lib(model: str | None = None):
         L.adm1_diffuse.restype = ctypes.c_int
         L.adm1_diffuse.argtypes = [vp, vp, i64, vp, i64, dbl, i32, vp, vp]
         L.adm1_model_name.restype = ctypes.c_char_p
+        L.adm1_set_phase_kinetics.restype = ctypes.c_int
+        L.adm1_set_phase_kinetics.argtypes = [vp, vp, i32]
         want = "adm1" if model is None else model
         got = L.adm1_model_name().decode()
         if got != want:
@@ -183,8 +185,8 @@ def _check(rc: int, what: str):
         raise ADM1Error(rc, what)
 
 
-def feed_struct(D, idx, S_in) -> adm1_feed:
-    return adm1_feed(_ptr(D), _ptr(idx), _ptr(S_in), int(S_in.shape[0]))
+def feed_struct(D, idx, S_in, phase=None) -> adm1_feed:
+    return adm1_feed(_ptr(D), _ptr(idx), _ptr(S_in), int(S_in.shape[0]), _ptr(phase))
 
 
 # ---------------------------------------------------------------------------
@@ -398,6 +400,17 @@ def adm1_set_launch(ctx: int, variant: int, blocks_per_cu: int = 0):
 ORDER_INDEX, ORDER_COST = 0, 1
 
 
+MAX_PHASES = 256
+
+
+def adm1_set_phase_kinetics(ctx: int, kin):
+    """Kinetic factor of phase ids 0..len(kin)-1 (host values; every other id
+    gets 1)."""
+    k = np.ascontiguousarray(kin, dtype=np.float64).ravel()
+    _check(_L(ctx).adm1_set_phase_kinetics(ctx, k.ctypes.data if k.size else None,
+                                           int(k.size)), "adm1_set_phase_kinetics")
+
+
 def adm1_set_service_batch(ctx: int, pairs: int):
     _check(_L(ctx).adm1_set_service_batch(ctx, int(pairs)), "adm1_set_service_batch")
 
@@ -466,37 +479,41 @@ class Context:
         except Exception:
             pass
 
+    def set_phase_kinetics(self, kin):
+        adm1_set_phase_kinetics(self.handle, kin)
+
     def step(self, state, T, D, fidx, S_in, dt, n=None, H=None, hlast=None, status=None,
-             nsteps=None, stream=None):
+             nsteps=None, stream=None, phase=None):
         import torch
         n = state.shape[1] if n is None else n
         if status is None:
             status = torch.empty(n, dtype=torch.uint8, device=state.device)
-        feed = feed_struct(D, fidx, S_in)
+        feed = feed_struct(D, fidx, S_in, phase)
         aux = None if H is None and hlast is None else adm1_aux(_ptr(H), _ptr(hlast))
         adm1_step_particles(self.handle, state, state.shape[1], T, feed, dt, n, aux, status,
                             nsteps, stream)
         return status
 
     def step_fixed(self, state, T, D, fidx, S_in, dt, substeps, method=FIXED_EULER, n=None,
-                   H=None, status=None, newton=None, stream=None):
+                   H=None, status=None, newton=None, stream=None, phase=None):
         """The fixed-step explicit scheme (adm1_step_fixed) in place."""
         import torch
         n = state.shape[1] if n is None else n
         if status is None:
             status = torch.empty(n, dtype=torch.uint8, device=state.device)
-        adm1_step_fixed(self.handle, state, state.shape[1], T, feed_struct(D, fidx, S_in), dt,
-                        substeps, method, n, H, status, newton, stream)
+        adm1_step_fixed(self.handle, state, state.shape[1], T,
+                        feed_struct(D, fidx, S_in, phase), dt, substeps, method, n, H, status,
+                        newton, stream)
         return status
 
-    def rhs(self, state, T, D, fidx, S_in, n=None, rate_precision=0, stream=None):
+    def rhs(self, state, T, D, fidx, S_in, n=None, rate_precision=0, stream=None, phase=None):
         import torch
         n = state.shape[1] if n is None else n
         ld = state.shape[1]
         dxdt = torch.empty((ND, ld), dtype=torch.float64, device=state.device)
         H = torch.empty(n, dtype=torch.float64, device=state.device)
         st = torch.empty(n, dtype=torch.uint8, device=state.device)
-        adm1_rhs(self.handle, state, ld, T, feed_struct(D, fidx, S_in), n, dxdt, ld, H,
+        adm1_rhs(self.handle, state, ld, T, feed_struct(D, fidx, S_in, phase), n, dxdt, ld, H,
                  rate_precision, st, stream)
         return dxdt, H, st
 
@@ -513,13 +530,13 @@ class Context:
     def last_failures(self, stream=None) -> dict:
         return adm1_last_failures(self.handle, stream)
 
-    def jacobian(self, state, T, D, fidx, S_in, n=None, stream=None):
+    def jacobian(self, state, T, D, fidx, S_in, n=None, stream=None, phase=None):
         import torch
         n = state.shape[1] if n is None else n
         J = torch.empty((n, ND, ND), dtype=torch.float64, device=state.device)
         st = torch.empty(n, dtype=torch.uint8, device=state.device)
-        adm1_jacobian(self.handle, state, state.shape[1], T, feed_struct(D, fidx, S_in), n, J,
-                      st, stream)
+        adm1_jacobian(self.handle, state, state.shape[1], T,
+                      feed_struct(D, fidx, S_in, phase), n, J, st, stream)
         return J, st
 
     def gas_flux(self, state, T, V_liq=None, n=None, stream=None):

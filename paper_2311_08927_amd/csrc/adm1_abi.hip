@@ -237,7 +237,15 @@ int check_feed(const adm1_feed* feed)
     if (feed->n_feed < 1) return ADM1_E_FEED;
     if (!is_device(feed->D) || !is_device(feed->idx) || !is_device(feed->S_in))
         return ADM1_E_NOT_DEVICE;
+    if (feed->phase && !is_device(feed->phase)) return ADM1_E_NOT_DEVICE;
     return ADM1_OK;
+}
+
+int check_feed_no_phase(const adm1_feed* feed)
+{
+    const int rc = check_feed(feed);
+    if (rc) return rc;
+    return feed->phase ? ADM1_E_FEED : ADM1_OK;
 }
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? ADM1_OK : (int)e; }
@@ -262,6 +270,18 @@ int finish_capture(hipStream_t s, int rc, adm1_graph* g, adm1_graph** out)
 }  // namespace adm1_abi
 
 using namespace adm1_abi;
+
+namespace {
+// The phase table of a context: kin[0..n-1], then 1 for every other id.
+int set_phase_table(adm1_ctx* c, const double* kin, int32_t n)
+{
+    double t[ADM1_MAX_PHASES];
+    for (int k = 0; k < ADM1_MAX_PHASES; ++k) t[k] = k < n ? kin[k] : 1.0;
+    if (hipMemcpy(c->d_phase_kin, t, sizeof(t), hipMemcpyHostToDevice) != hipSuccess)
+        return (int)hipGetLastError();
+    return ADM1_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -325,6 +345,8 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
         hipMalloc(&c->d_fail, adm1::kFailSlots * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(c->d_fail, 0, adm1::kFailSlots * sizeof(unsigned long long)) !=
             hipSuccess ||
+        hipMalloc(&c->d_phase_kin, ADM1_MAX_PHASES * sizeof(double)) != hipSuccess ||
+        set_phase_table(c, nullptr, 0) != ADM1_OK ||
         static_scratch(c->device, &c->static_scratch) != ADM1_OK) {
         (void)hipGetLastError();
         if (c->d_queue) (void)hipFree(c->d_queue);
@@ -333,6 +355,7 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
         if (c->d_order) (void)hipFree(c->d_order);
         if (c->d_order_work) (void)hipFree(c->d_order_work);
         if (c->d_fail) (void)hipFree(c->d_fail);
+        if (c->d_phase_kin) (void)hipFree(c->d_phase_kin);
         delete c;
         return ADM1_E_NOMEM;
     }
@@ -362,7 +385,18 @@ void adm1_destroy(adm1_ctx* ctx)
     (void)hipFree(ctx->d_order);
     (void)hipFree(ctx->d_order_work);
     (void)hipFree(ctx->d_fail);
+    (void)hipFree(ctx->d_phase_kin);
     delete ctx;
+}
+
+int adm1_set_phase_kinetics(adm1_ctx* ctx, const double* kin, int32_t n_phases)
+{
+    if (!ctx) return ADM1_E_NULL;
+    if (n_phases < 0 || n_phases > ADM1_MAX_PHASES) return ADM1_E_OPTS;
+    if (n_phases > 0 && !kin) return ADM1_E_NULL;
+    for (int32_t k = 0; k < n_phases; ++k)
+        if (!std::isfinite(kin[k]) || kin[k] < 0.0) return ADM1_E_OPTS;
+    return set_phase_table(ctx, kin, n_phases);
 }
 
 namespace {
@@ -406,6 +440,7 @@ int step_dispatch(adm1_ctx* ctx, const StepScratch& w, double* state, int64_t ld
     a.p = ctx->dp;
     a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.D = feed->D; a.fidx = feed->idx;
     a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.dt = dt_days;
+    a.phase = feed->phase; a.phase_kin = ctx->d_phase_kin;
     a.H = aux ? aux->H : nullptr;
     a.hlast = aux ? aux->h_last : nullptr;
     a.status = status; a.nsteps = nsteps; a.queue = w.queue;
@@ -496,6 +531,7 @@ int adm1_step_fixed(adm1_ctx* ctx, double* state, int64_t ld, const double* temp
     a.p = ctx->dp;
     a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.D = feed->D; a.fidx = feed->idx;
     a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.dt = dt_days; a.substeps = substeps;
+    a.phase = feed->phase; a.phase_kin = ctx->d_phase_kin;
     a.method = method; a.H = H; a.status = status; a.newton = newton;
     rc = hip_rc(adm1::launch_fixed(a, ctx->opts.rate_precision, (hipStream_t)stream));
     if (rc) return rc;
@@ -596,6 +632,7 @@ int adm1_rhs(adm1_ctx* ctx, const double* state, int64_t ld, const double* temp_
     a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.D = feed->D; a.fidx = feed->idx;
     a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.dxdt = dxdt; a.ld_out = ld_out; a.H_out = H_out;
     a.status = status;
+    a.phase = feed->phase; a.phase_kin = ctx->d_phase_kin;
     return hip_rc(adm1::launch_rhs(a, rate_precision, (hipStream_t)stream));
 }
 
@@ -614,6 +651,7 @@ int adm1_jacobian(adm1_ctx* ctx, const double* state, int64_t ld, const double* 
     a.p = ctx->dp;
     a.state = state; a.ld = ld; a.n = n; a.T = temp_K; a.D = feed->D; a.fidx = feed->idx;
     a.S_in = feed->S_in; a.n_feed = feed->n_feed; a.status = status;
+    a.phase = feed->phase; a.phase_kin = ctx->d_phase_kin;
     return hip_rc(adm1::launch_jacobian(a, J, (hipStream_t)stream));
 }
 

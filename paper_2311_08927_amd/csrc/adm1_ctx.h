@@ -24,6 +24,7 @@ struct adm1_ctx {
     int32_t* d_order_work;  // its histogram, bucket cursors and length
     unsigned long long* d_fail;  // outcome counters of the last step call [kFailSlots]
     int32_t* static_scratch;     // this device's address of the library's static scratch
+    double* d_phase_kin;  // kinetic factor of each phase id [ADM1_MAX_PHASES]
 };
 
 // A captured coupling step (adm1_graph_capture_step and its surrogate
@@ -37,6 +38,8 @@ namespace adm1_abi {
 bool is_device(const void* ptr);
 int check_layout(const adm1_ctx* ctx, int64_t ld, int64_t n);
 int check_feed(const adm1_feed* feed);
+// check_feed, and no phases (calls that do not model them)
+int check_feed_no_phase(const adm1_feed* feed);
 int hip_rc(hipError_t e);
 // End a capture begun on s, instantiate the graph into *g (freed on error).
 int finish_capture(hipStream_t s, int rc, adm1_graph* g, adm1_graph** out);

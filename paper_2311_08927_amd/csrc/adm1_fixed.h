@@ -25,6 +25,8 @@ struct FixedArgs {
     double* H;           // nullable: S_H+ warm start in, root out
     uint8_t* status;
     int32_t* newton;     // nullable: algebraic Newton iterations per particle
+    const uint8_t* phase;      // [n] nullable: phase id per particle
+    const double* phase_kin;   // [256] kinetic factor per phase id
 };
 
 hipError_t launch_fixed(const FixedArgs& a, int rate_precision, hipStream_t s);

@@ -27,6 +27,8 @@ struct StepArgs {
     int64_t index_bound;    // host upper bound of that count (0: unknown)
     const DevParams* pdev;  // device copy of p (read through the scalar cache)
     int32_t service_batch;  // persistent kernel: pairs served together (0: default)
+    const uint8_t* phase;      // [n] nullable: phase id per particle
+    const double* phase_kin;   // [256] kinetic factor per phase id
 };
 
 struct RhsArgs {
@@ -42,6 +44,8 @@ struct RhsArgs {
     int64_t ld_out;
     double* H_out;
     uint8_t* status;
+    const uint8_t* phase;      // [n] nullable: phase id per particle
+    const double* phase_kin;   // [256] kinetic factor per phase id
 };
 
 struct GasArgs {

@@ -301,7 +301,8 @@ __global__ void __launch_bounds__(64, 1) k_step1(StepArgs a)
         if (!fin) {
             st = 4;
         } else {
-            const TConst c = tconst(p, T);
+            TConst c = tconst(p, T);
+            c.arr *= phase_factor(a.phase, a.phase_kin, i);
             st = integrate1<R, Lin>(p, c, y, D, sin, a.dt, H, Sh2, hl, cnt);
             if (st == 0) {
                 store_state(p, c, a.state, a.ld, i, y, H, Sh2);
@@ -350,7 +351,8 @@ __device__ __forceinline__ void fixed_body(const FixedArgs& a)
             if (!isfinite(sin[k])) st = 4;
     }
     if (st == 0) {
-        const TConst c = tconst(p, T);
+        TConst c = tconst(p, T);
+        c.arr *= phase_factor(a.phase, a.phase_kin, i);
         const double h = a.dt / a.substeps;
         double f[NY];
         for (int s = 0; s < a.substeps && st == 0; ++s) {
@@ -430,7 +432,8 @@ __global__ void __launch_bounds__(64) k_rhs(RhsArgs a)
     const DevParams& p = a.p;
     double y[NY], f[NY];
     for (int k = 0; k < NY; ++k) y[k] = a.state[state_row(k) * a.ld + i];
-    const TConst c = tconst(p, a.T[i]);
+    TConst c = tconst(p, a.T[i]);
+    c.arr *= phase_factor(a.phase, a.phase_kin, i);
     const int fi = a.fidx[i];
     if (fi < 0 || fi >= a.n_feed) {
         for (int k = 0; k < NY; ++k) a.dxdt[k * a.ld_out + i] = NAN;
@@ -518,7 +521,8 @@ __global__ void __launch_bounds__(64) k_jacobian(RhsArgs a, double* J)
     const DevParams& p = a.p;
     double y[NY], f[NY], M[NB * NB];
     for (int k = 0; k < NY; ++k) y[k] = a.state[state_row(k) * a.ld + i];
-    const TConst c = tconst(p, a.T[i]);
+    TConst c = tconst(p, a.T[i]);
+    c.arr *= phase_factor(a.phase, a.phase_kin, i);
     double* Jo = J + i * NY * NY;
     const int fi = a.fidx[i];
     if (fi < 0 || fi >= a.n_feed) {

@@ -71,6 +71,15 @@ __device__ __forceinline__ TConst tconst(const DevParams& p, double T)
     return c;
 }
 
+// The kinetic factor of particle i's phase (sec. 5, several particle kinds):
+// it scales every biochemical rate, and every rate carries the Arrhenius
+// factor, so callers multiply TConst::arr by it.  No phase array: factor 1.
+__device__ __forceinline__ double phase_factor(const uint8_t* phase, const double* kin,
+                                               int64_t i)
+{
+    return phase ? kin[phase[i]] : 1.0;
+}
+
 // ---------------------------------------------------------------------------
 // Eq. 7: charge balance E(S_H+) and dE/dS_H+.  The ions are the equilibrium
 // fractions K/(K + S_H+) of their totals.

@@ -257,6 +257,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                 run = false;
             } else {
                 c = tconst_ool(&p, T);
+                c.arr *= phase_factor(a.phase, a.phase_kin, i);
                 if (!odd) {
                     L.tc[0][pr] = c.RT; L.tc[1][pr] = c.K_w; L.tc[2][pr] = c.K_a_co2;
                     L.tc[3][pr] = c.K_a_IN; L.tc[4][pr] = c.K_H_h2; L.tc[5][pr] = c.K_H_ch4;

@@ -557,7 +557,7 @@ int adm1_surrogate_gate(adm1_surrogate* s, double* state, int64_t ld, const doub
     if ((rc = check_layout(s->ctx, ld, n))) return rc;
     if (n > INT32_MAX) return ADM1_E_SIZE;
     if (!(dt_days > 0.0) || !std::isfinite(dt_days)) return ADM1_E_DT;
-    if ((rc = check_feed(feed))) return rc;
+    if ((rc = check_feed_no_phase(feed))) return rc;  // the surrogate models no phases
     if (!(gate->max_dlog >= 0.0) || !(gate->tol_ion >= 0.0) || !(gate->tol_closure >= 0.0))
         return ADM1_E_OPTS;
     if (!is_device(state) || !is_device(temp_K) || !is_device(Y) || !is_device(status) ||
@@ -594,7 +594,7 @@ int adm1_surrogate_step(adm1_surrogate* s, double* state, int64_t ld, const doub
 {
     int rc = check_surrogate(s);
     if (rc) return rc;
-    if (!feed) return ADM1_E_NULL;
+    if ((rc = check_feed_no_phase(feed))) return rc;  // the surrogate models no phases
     if (n > s->n_max) return ADM1_E_SIZE;
     if (fb_count && !is_device(fb_count)) return ADM1_E_NOT_DEVICE;
     if (aux && aux->h_last && !is_device(aux->h_last)) return ADM1_E_NOT_DEVICE;
@@ -648,6 +648,7 @@ int adm1_surrogate_graph_capture_step(adm1_surrogate* s, double* state, int64_t 
     int rc = check_surrogate(s);
     if (rc) return rc;
     if (!out || !stream || !feed || !gate) return ADM1_E_NULL;
+    if ((rc = check_feed_no_phase(feed))) return rc;  // the surrogate models no phases
     if (n < 0 || n > s->n_max) return ADM1_E_SIZE;
     if (!(gate->max_dlog >= 0.0) || !(gate->tol_ion >= 0.0) || !(gate->tol_closure >= 0.0))
         return ADM1_E_OPTS;

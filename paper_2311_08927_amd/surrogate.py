@@ -244,14 +244,17 @@ class Surrogate:
         return Y[:n]
 
     def step(self, state, T, D, fidx, S_in, dt, gate: adm1_gate, n=None, H=None, hlast=None,
-             status=None, nsteps=None, route=None, fb_count=None, stream=None):
+             status=None, nsteps=None, route=None, fb_count=None, stream=None, phase=None):
+        """One gated step (phase: passed through; the library refuses phases
+        here, since the surrogate models one phase)."""
         import torch
         n = state.shape[1] if n is None else n
         if status is None:
             status = torch.empty(max(n, 1), dtype=torch.uint8, device=state.device)
         aux = None if H is None and hlast is None else A.adm1_aux(_p(H), _p(hlast))
-        adm1_surrogate_step(self.handle, state, state.shape[1], T, A.feed_struct(D, fidx, S_in),
-                            dt, n, gate, aux, status, nsteps, route, fb_count, stream)
+        adm1_surrogate_step(self.handle, state, state.shape[1], T,
+                            A.feed_struct(D, fidx, S_in, phase), dt, n, gate, aux, status,
+                            nsteps, route, fb_count, stream)
         return status
 
     def train_step(self, X, target, lr, step, loss):

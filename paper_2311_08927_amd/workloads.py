@@ -208,3 +208,20 @@ def subset(w: Workload, idx: np.ndarray) -> Workload:
     return Workload(w.name + "_subset", m, ld, X, w.T[idx].copy(), w.D[idx].copy(),
                     w.fidx[idx].copy(), w.feed, w.dt, w.steps, w.rtol,
                     None if w.zone is None else w.zone[idx].copy(), dict(w.extra))
+
+
+# Particle phases (sec. 5, several particle kinds): an active liquid phase,
+# a settled sediment phase with reduced biological activity and an inert
+# phase with none.  The factors scale every biochemical rate of a particle.
+PHASE_KIN = np.array([1.0, 0.25, 0.0])
+PHASE_SHARES = (0.7, 0.2, 0.1)
+
+
+def mixed_phases(n: int, seed: int, ld: int | None = None) -> np.ndarray:
+    """uint8 phase ids [ld] (0 beyond n): each particle draws phase k with
+    probability PHASE_SHARES[k]."""
+    ld = n if ld is None else ld
+    rng = np.random.default_rng(seed + 9001)
+    ph = np.zeros(ld, dtype=np.uint8)
+    ph[:n] = rng.choice(len(PHASE_SHARES), size=n, p=PHASE_SHARES).astype(np.uint8)
+    return ph
