@@ -31,6 +31,7 @@ next to this script, or into DIR)
 from __future__ import annotations
 
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -569,15 +570,30 @@ def emit_sparse2():
     for k in range(0, len(decl), 10):
         out.append("    double " + ", ".join(decl[k:k + 10]) + "; \\")
     out.append("    (void)0")
-    # assembly
+    # assembly.  The parameters are read into locals first: both sides of
+    # each lane-dependent select then are plain values, so the select stays
+    # a per-lane choice instead of becoming a branch around a memory load
+    # (every wave holds both sides, so a branch runs both anyway).
     out.append("#define ADM1_SP2_BUILD(alpha, D) \\")
+    body, hoist = [], {}
+
+    def hoisted(e):
+        def sub(mt):
+            ref = mt.group(0)
+            if ref not in hoist:
+                hoist[ref] = f"q{len(hoist)}"
+            return hoist[ref]
+        return re.sub(r"\bp\.[A-Za-z_]\w*(?:\[\d+\])?", sub, e)
     for m, (a, b) in enumerate(pairs):
         for c in slots[m]:
-            e0, e1 = cexpr(a, c), cexpr(b, c)
+            e0, e1 = hoisted(cexpr(a, c)), hoisted(cexpr(b, c))
             if e0 == e1:
-                out.append(f"    w{m}_{c} = {e0}; \\")
+                body.append(f"    w{m}_{c} = {e0}; \\")
             else:
-                out.append(f"    w{m}_{c} = odd ? ({e1}) : ({e0}); \\")
+                body.append(f"    w{m}_{c} = odd ? ({e1}) : ({e0}); \\")
+    for ref, name in hoist.items():
+        out.append(f"    const double {name} = {ref}; \\")
+    out += body
     out.append("    (void)0")
 
     def role(q, k, structural):
