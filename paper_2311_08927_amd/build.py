@@ -67,14 +67,40 @@ def build(verbose: bool = False, model: str | None = None) -> str:
     return out
 
 
+LU_BENCH_DIR = os.path.join(PKG, "_build", "lu_bench")
+LU_BENCH = os.path.join(LU_BENCH_DIR, "lu_group_bench")
+
+
+def build_lu_bench(verbose: bool = False) -> str:
+    """The lanes-per-particle measurement of the sparse LU (a standalone
+    program, csrc/lu_group_bench.hip; run it with [particles] [repeats])."""
+    subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_lu_groups.py"), "--out",
+                           LU_BENCH_DIR])
+    tmp = LU_BENCH + ".tmp"
+    cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",
+           f"-I{LU_BENCH_DIR}", "-o", tmp, os.path.join(CSRC, "lu_group_bench.hip")]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(tmp, LU_BENCH)
+    return LU_BENCH
+
+
 def build_all(verbose: bool = False) -> list[str]:
-    return [build(verbose)] + [build(verbose, m) for m in VARIANT_MODELS]
+    return [build(verbose)] + [build(verbose, m) for m in VARIANT_MODELS] + \
+        [build_lu_bench(verbose)]
 
 
 if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser()
     ap.add_argument("--model", default=None, help="model description (default: standard)")
-    ap.add_argument("--all", action="store_true", help="standard and variant descriptions")
+    ap.add_argument("--all", action="store_true",
+                    help="standard and variant descriptions, and the LU lanes measurement")
+    ap.add_argument("--lu-bench", action="store_true", help="only the LU lanes measurement")
     a = ap.parse_args()
-    print(build_all(True) if a.all else build(True, a.model))
+    if a.lu_bench:
+        print(build_lu_bench(True))
+    else:
+        print(build_all(True) if a.all else build(True, a.model))
