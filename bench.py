@@ -34,7 +34,8 @@ FIXED_PARTICLES = 110_929
 # Sources of the step kernel: HBM traffic measured with hardware counters is
 # reported only while they are unchanged since the measurement.
 STEP_SOURCES = ["adm1_step_sparse2.hip", "adm1_model.h", "adm1_jac_sparse2.inc",
-                "adm1_partials.inc", "adm1_devparams.h", "adm1_rodas4.h", "adm1_kernels.h"]
+                "adm1_partials.inc", "adm1_stoich.inc", "adm1_devparams.h", "adm1_rodas4.h",
+                "adm1_kernels.h"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_sparse2_batched_2e20.md")
 
 
@@ -331,6 +332,7 @@ def main():
                    "launch": tune["layout"] if tune else launch,
                    "autotune": None if tune is None else
                    {"sample": tune["sample"], "cached": bool(tune.get("cached")),
+                    "source": tune.get("source", "tuned in this run"),
                     "timings_ms": tune["timings_ms"]}},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic,

@@ -11,7 +11,9 @@ candidate from the same start state):
     (1-4) and the service batch (pairs restarted together: 1, 2, 4, 8).
 The fastest is set on the context (adm1_set_launch, adm1_set_service_batch),
 so the default step path (opts.variant = -1) uses it.  Choices are cached in
-a JSON file keyed by GPU architecture, sample size, tolerance and tag.
+a JSON file keyed by GPU architecture, sample size, tolerance and tag; the
+package ships the choices measured on gfx950 (data/autotune_choices.json),
+so a fresh machine of that architecture starts from them.
 """
 from __future__ import annotations
 
@@ -48,18 +50,29 @@ def apply(ctx: "A.Context", choice):
 
 CACHE = os.environ.get("ADM1_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "adm1_autotune.json"))
+# choices measured once per architecture and shipped with the package; a
+# user cache entry with the same key takes precedence
+PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
+                        "autotune_choices.json")
 
 
 def _key(arch: str, n: int, rtol: float, tag: str) -> str:
     return f"{arch}|n={n}|rtol={rtol:g}|{tag}"
 
 
-def load_cache() -> dict:
+def _read(path: str) -> dict:
     try:
-        with open(CACHE) as fh:
+        with open(path) as fh:
             return json.load(fh)
     except (OSError, ValueError):
         return {}
+
+
+def load_cache() -> dict:
+    """Packaged choices, overridden by the user cache."""
+    d = {k: dict(v, source="packaged") for k, v in _read(PACKAGED).items()}
+    d.update({k: dict(v, source="user cache") for k, v in _read(CACHE).items()})
+    return d
 
 
 def save_cache(d: dict):
@@ -86,6 +99,7 @@ def autotune(ctx: "A.Context", X, T, D, fidx, S_in, dt, n=None, tag="", repeats=
     if key in cache and len(cache[key].get("choice", [])) == 3:
         apply(ctx, cache[key]["choice"])
         return dict(cache[key], cached=True)
+    cache = _read(CACHE) if use_cache else {}
     saved_variant = ctx.opts.variant
     ctx.set_opts(variant=-1)
     timings = {}

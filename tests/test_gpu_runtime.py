@@ -77,6 +77,7 @@ def test_autotune_and_launch_setting(torch_cuda, tmp_path, monkeypatch):
     from paper_2311_08927_amd import adm1 as A
     from paper_2311_08927_amd import autotune as AT
     monkeypatch.setattr(AT, "CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(AT, "PACKAGED", str(tmp_path / "packaged.json"))
     w = W.batched_population(8192, seed=8)
     ctx = make_ctx(w.ld)
     dw = DeviceWorkload(w)
@@ -92,7 +93,14 @@ def test_autotune_and_launch_setting(torch_cuda, tmp_path, monkeypatch):
     print("autotune:", res["layout"], {k: round(v, 2) for k, v in res["timings_ms"].items()})
     # cached second call
     res2 = AT.autotune(ctx, dw.X, dw.T, dw.D, dw.fidx, dw.S_in, w.dt, n=w.n, tag="test")
-    assert res2["choice"] == res["choice"]
+    assert res2["choice"] == res["choice"] and res2["source"] == "user cache"
+    # a packaged choice is used when the user cache has none
+    import json
+    key = next(iter(json.load(open(tmp_path / "tune.json"))))
+    (tmp_path / "packaged.json").write_text(json.dumps({key: dict(res, choice=[2, 2, 8])}))
+    (tmp_path / "tune.json").unlink()
+    res3 = AT.autotune(ctx, dw.X, dw.T, dw.D, dw.fidx, dw.S_in, w.dt, n=w.n, tag="test")
+    assert res3["choice"] == [2, 2, 8] and res3["source"] == "packaged" and res3["cached"]
     # the tuned launch gives the oracle's answer on a slice
     sub = W.subset(w, np.arange(0, w.n, 97))
     dsub = DeviceWorkload(sub)
