@@ -173,7 +173,10 @@ typedef struct adm1_ctx adm1_ctx;
  * Derives the stoichiometric closures (inorganic C and N rows of the Petersen
  * matrix of eq. 2) and checks COD continuity of every process; copies the
  * parameters into the context.  Allocates the context scratch (work-queue
- * counters and reduction buffers).  Synchronous.  *out is set on success. */
+ * counters and reduction buffers).  Synchronous.  *out is set on success.
+ * ADM1_E_PARAMS also when a Hill exponent of eqs. 3-4, 3 / (pH_UL - pH_LL),
+ * is not an integer from 1 to 4 (the standard set gives 2, 3 and 3): the
+ * kernels take that power by multiplication. */
 int adm1_init(const adm1_params *p, const adm1_opts *o, int64_t n_max, adm1_ctx **out);
 
 /* Replace the integration options (host struct) of a context.  Synchronous. */
@@ -583,6 +586,18 @@ int adm1_surrogate_graph_capture_step(adm1_surrogate *s, double *state, int64_t 
 int adm1_surrogate_train_step(adm1_surrogate *s, const uint16_t *X, const float *target,
                               int64_t B, float lr, int32_t step, float *loss, void *stream);
 
+/* Mean residual and mean squared residual of the network, per output
+ * column: over rows 0..n-1 of X (BF16 features [n][ADM1_MLP_FEAT_LD],
+ * device) and target (float32 [n][ADM1_MLP_OUT], device, standardised
+ * units), mean_out[c] = mean(Y[r][c] - target[r][c]) and msq_out[c] =
+ * mean((Y - target)^2) for c < ADM1_MLP_OUT (HOST memory of 35 float64
+ * each); the forward pass runs `chunk` rows at a time.  Sums in FP64 in a
+ * fixed order (bit-reproducible).  Allocates a chunk of outputs and the
+ * partial sums for the call.  Synchronous. */
+int adm1_surrogate_residual_stats(adm1_surrogate *s, const uint16_t *X, const float *target,
+                                  int64_t n, int64_t chunk, double *mean_out, double *msq_out,
+                                  void *stream);
+
 /* Free the surrogate.  Synchronous.  NULL is a no-op. */
 void adm1_surrogate_destroy(adm1_surrogate *s);
 
@@ -596,6 +611,31 @@ const char *adm1_param_names(void);
  * factor (the table is then unchanged).  Synchronous.  Not supported by the
  * surrogate calls (a feed with phases is ADM1_E_FEED there). */
 int adm1_set_phase_kinetics(adm1_ctx *ctx, const double *kin, int32_t n_phases);
+
+/* ------------------------------------------------------------------------
+ * Data handling of the surrogate's training driver, on the device.
+ * ------------------------------------------------------------------------ */
+/* dst row j = src row idx[j] for j < n_idx, rows of row_bytes bytes (a
+ * multiple of 4; src and dst 4-byte aligned); src has n_src rows, and an
+ * index outside [0, n_src) yields a zero row.  Device arrays; idx int32.
+ * Asynchronous on `stream`. */
+int adm1_gather_rows(const void *src, int64_t n_src, int64_t row_bytes, const int32_t *idx,
+                     int64_t n_idx, void *dst, void *stream);
+
+/* out[0..n-1] (int32, device) = a permutation of 0..n-1 determined by
+ * `seed`: a four-round Feistel network on the smallest even bit width
+ * covering n, restricted to [0, n) by cycle walking.  n <= 2^31 - 1.
+ * Asynchronous on `stream`. */
+int adm1_permutation(int64_t n, uint64_t seed, int32_t *out, void *stream);
+
+/* Per-column mean and sample standard deviation (divisor n - 1) of the
+ * first `cols` (<= 64) columns of a row-major device array of n >= 2 rows
+ * and ld elements per row, float32 (bf16 = 0) or BF16 bit patterns
+ * (bf16 = 1), summed in FP64 in a fixed order (two passes, the second about
+ * the mean).  mean_out, sd_out: HOST memory of cols float64.  Allocates its
+ * partial sums for the call.  Synchronous. */
+int adm1_column_stats(const void *data, int32_t bf16, int64_t n, int32_t cols, int64_t ld,
+                      double *mean_out, double *sd_out, void *stream);
 
 /* Name of the model description this library was generated from (sec. 2.2,
  * eq. 2: the Petersen matrix as data; static string): "adm1" for the

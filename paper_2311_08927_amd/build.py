@@ -25,7 +25,7 @@ VARIANT_MODELS = [os.path.join(DATA, "adm1_petersen_decay_to_particulates.json")
 ARCH = os.environ.get("ADM1_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["adm1_abi.hip", "adm1_kernels.hip", "adm1_step_sparse2.hip", "adm1_order.hip",
            "adm1_transport.hip", "adm1_mlp.hip", "adm1_surrogate.hip",
-           "adm1_diffusion.hip", "adm1_snapshot.cpp"]
+           "adm1_diffusion.hip", "adm1_train.hip", "adm1_snapshot.cpp"]
 
 
 def hipcc() -> str:

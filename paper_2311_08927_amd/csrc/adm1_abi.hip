@@ -135,7 +135,9 @@ int derive(const adm1_params& p, DevParams& d)
         d.pH_K[k] = std::pow(10.0, -0.5 * (ll[k] + ul[k]));
         d.pH_invK[k] = 1.0 / d.pH_K[k];
         const double r = std::nearbyint(d.pH_n[k]);
-        d.pH_nint[k] = (std::fabs(d.pH_n[k] - r) < 1e-12 && r >= 1 && r <= 4) ? (int)r : 0;
+        // the kernels take the Hill power by multiplication: exponents 1..4
+        if (!(std::fabs(d.pH_n[k] - r) < 1e-12 && r >= 1 && r <= 4)) return ADM1_E_PARAMS;
+        d.pH_nint[k] = (int)r;
     }
 
     double nu[eNLIQ][19];

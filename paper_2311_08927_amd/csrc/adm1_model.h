@@ -177,29 +177,18 @@ __device__ __forceinline__ int solve_Sh2(const DevParams& p, const H2Terms& t, d
     return 1;
 }
 
-// r^n for a non-integer Hill exponent, kept out of line: the standard
-// parameter set has integer exponents, and inlined exp/log would leave their
-// polynomial constants live in registers of the kernels that inline this.
-static __device__ __attribute__((noinline)) double pow_ool(double r, double n)
-{
-    return exp2(n * log2(r));
-}
-static __device__ __attribute__((noinline)) float pow_ool(float r, float n)
-{
-    return exp2f(n * log2f(r));
-}
-
 // pH inhibition, eqs. 3-4 written in S_H+: 1 / (1 + (S_H+/K)^n).
 template <typename R>
 __device__ __forceinline__ R inhib_pH(R H, double invK, double n, int nint)
 {
     const R r = H * (R)invK;
     R rn;
+    // integer exponents 1..4 only (adm1_init refuses others): no call to a
+    // power routine, which would run under a partial exec mask here
     if (nint == 1) rn = r;
     else if (nint == 2) rn = r * r;
     else if (nint == 3) rn = r * r * r;
-    else if (nint == 4) { const R r2 = r * r; rn = r2 * r2; }
-    else rn = pow_ool(r, (R)n);
+    else { const R r2 = r * r; rn = r2 * r2; }
     return frcp((R)1 + rn);
 }
 

@@ -111,6 +111,10 @@ __device__ __forceinline__ TConst load_tc(const Lds& L, int pr)
 
 // Rarely executed transcendental work (once per particle) kept out of line,
 // so that the constants of exp/log are not hoisted into the persistent loop.
+// They are called only where every lane of the wave is active: a call made
+// under a partial exec mask may overwrite the values the inactive lanes hold
+// in caller-saved registers (measured: warm-start guesses of waiting pairs
+// changed, making a particle's rounding depend on its neighbours).
 __device__ __attribute__((noinline)) TConst tconst_ool(const DevParams* p, double T)
 {
     return tconst(*p, T);
@@ -160,7 +164,7 @@ struct PairState {
     double y[NDP];  // own components of the particle's state
 };
 
-enum Job { kNone = 0, kFinish = 1, kStart = 2, kHinit = 3 };
+enum Job { kNone = 0, kFinish = 1, kStart = 2, kHinit = 3, kRoot = 4 };
 
 __device__ __forceinline__ void write_status(const StepArgs& a, const PairState& s, int st,
                                              bool odd)
@@ -191,7 +195,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
     const bool odd = lane & 1;
     const int pr = lane >> 1;
     double yin[NY], f[NY], f0[NY];
-    double h0 = 0.0, d1 = 0.0;
+    double h0 = 0.0, d1 = 0.0, dm = 0.0;
     for (;;) {
         const bool need = !active && !exhausted && job == kNone;
         const unsigned long long needm = __ballot(need && !odd);
@@ -211,6 +215,23 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
             }
         }
         if (!__any(job != kNone)) break;
+        // the out-of-line helpers, here with every lane active: temperature
+        // constants of the particles being started, and the root of the
+        // starting-step estimate of those finishing it
+        // (the conditions are wave-uniform, so the exec mask stays full)
+        TConst cstart;
+        if (__any(job == kStart)) {
+            const DevParams& p0 = params_at(pp);
+            cstart = tconst_ool(&p0, job == kStart ? a.T[s.pid] : 300.0);
+        }
+        double root = 1.0;
+        if (__any(job == kRoot)) root = fifth_root(job == kRoot ? 0.01 / dm : 1.0);
+        if (job == kRoot) {
+            const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : root;
+            s.h = fmin(fmin(100.0 * h0, h1), a.dt);
+            active = true;
+            job = kNone;
+        }
         if (job == kNone) continue;
         const DevParams& p = params_at(pp);
         const int64_t i = s.pid;
@@ -256,7 +277,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                 job = kNone;
                 run = false;
             } else {
-                c = tconst_ool(&p, T);
+                c = cstart;
                 c.arr *= phase_factor(a.phase, a.phase_kin, i);
                 if (!odd) {
                     L.tc[0][pr] = c.RT; L.tc[1][pr] = c.K_w; L.tc[2][pr] = c.K_a_co2;
@@ -355,7 +376,6 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                 }
             }
         } else {  // kHinit
-            double h = h0;
             if (!rc) {
                 double d2 = 0.0;
 #pragma unroll
@@ -366,14 +386,13 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                     d2 += (v / sc) * (v / sc);
                 }
                 d2 = sqrt(d2 / NY) / h0;
-                const double dm = fmax(d1, d2);
-                const double h1 =
-                    (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : fifth_root(0.01 / dm);
-                h = fmin(fmin(100.0 * h0, h1), a.dt);
+                dm = fmax(d1, d2);
+                job = kRoot;  // the fifth root, at the next pass's uniform call
+            } else {
+                s.h = h0;
+                active = true;
+                job = kNone;
             }
-            s.h = h;
-            active = true;
-            job = kNone;
         }
     }
 }

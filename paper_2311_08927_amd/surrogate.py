@@ -54,6 +54,10 @@ def _lib():
                                     vp, vp],
             "adm1_surrogate_step": [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp, vp],
             "adm1_surrogate_train_step": [vp, vp, vp, i64, flt, i32, vp, vp],
+            "adm1_surrogate_residual_stats": [vp, vp, vp, i64, i64, vp, vp, vp],
+            "adm1_gather_rows": [vp, i64, i64, vp, i64, vp, vp],
+            "adm1_permutation": [i64, ctypes.c_uint64, vp, vp],
+            "adm1_column_stats": [vp, i32, i64, i32, i64, vp, vp, vp],
             "adm1_surrogate_graph_capture_step": [vp, vp, i64, vp, vp, dbl, i64, vp, vp, vp,
                                                   vp, vp, vp, vp, vp, vp, vp, vp,
                                                   ctypes.POINTER(vp)],
@@ -186,6 +190,40 @@ def adm1_surrogate_graph_capture_step(s, state, ld, temp_K, feed, dt_days, n, ga
     return g.value
 
 
+def adm1_gather_rows(src, idx, dst, stream=None):
+    """dst[j] = src[idx[j]] over rows (device tensors; rows of 4-byte words)."""
+    rb = src.stride(0) * src.element_size()
+    assert src.is_contiguous() and dst.is_contiguous() and dst.stride(0) * dst.element_size() == rb
+    _check(_lib().adm1_gather_rows(_p(src), int(src.shape[0]), int(rb), _p(idx),
+                                   int(idx.shape[0]), _p(dst), _s(stream)), "adm1_gather_rows")
+
+
+def adm1_permutation(n: int, seed: int, out, stream=None):
+    _check(_lib().adm1_permutation(int(n), int(seed) & (2**64 - 1), _p(out), _s(stream)),
+           "adm1_permutation")
+
+
+def adm1_column_stats(data, cols: int, bf16: bool, stream=None):
+    """(mean, sd) float64 of the first `cols` columns of a 2-D device tensor
+    (float32, or BF16 bit patterns in int16 with bf16=True)."""
+    mean = np.zeros(cols)
+    sd = np.zeros(cols)
+    _check(_lib().adm1_column_stats(_p(data), int(bool(bf16)), int(data.shape[0]), int(cols),
+                                    int(data.stride(0)), mean.ctypes.data, sd.ctypes.data,
+                                    _s(stream)), "adm1_column_stats")
+    return mean, sd
+
+
+def adm1_surrogate_residual_stats(s, X, target, chunk: int = 1 << 20, stream=None):
+    """(mean, mean square) float64 [35] of the network's residual on (X, target)."""
+    mean = np.zeros(OUT)
+    msq = np.zeros(OUT)
+    _check(_lib().adm1_surrogate_residual_stats(s, _p(X), _p(target), int(X.shape[0]),
+                                                int(chunk), mean.ctypes.data, msq.ctypes.data,
+                                                _s(stream)), "adm1_surrogate_residual_stats")
+    return mean, msq
+
+
 def adm1_surrogate_train_step(s, X, target, B, lr, step, loss, stream=None):
     _check(_lib().adm1_surrogate_train_step(s, _p(X), _p(target), int(B), float(lr), int(step),
                                             _p(loss), _s(stream)),
@@ -264,7 +302,8 @@ class Surrogate:
 def integrate_states(ctx, w: W.Workload, steps: int):
     """Advance w with the FP64 integrator for `steps` coupling intervals.
     Returns the device states X_0..X_steps ([35][ld] each), the dilution
-    rates of each interval and a mask [steps][n] of clean steps (status 0)."""
+    rates of each interval and a host mask [steps][n] of clean steps
+    (status 0)."""
     import torch
     dev = "cuda"
     X = torch.from_numpy(np.ascontiguousarray(w.X)).to(dev)
@@ -280,8 +319,8 @@ def integrate_states(ctx, w: W.Workload, steps: int):
         ctx.step(X, T, D, fidx, S_in, w.dt, n=w.n, H=H, hlast=hl, status=status)
         states.append(X.clone())
         Ds.append(D)
-        ok.append(status == 0)
-    return states, Ds, torch.stack(ok), T
+        ok.append(status.cpu().numpy()[:w.n] == 0)
+    return states, Ds, np.stack(ok), T
 
 
 def integrate_field_states(ctx, w: W.Workload, steps: int):
@@ -310,8 +349,8 @@ def integrate_field_states(ctx, w: W.Workload, steps: int):
         A.adm1_advect(pos, w.ld, w.n, flow, dt_s, W.advect_substeps(dt_s))
         states.append(X.clone())
         Ds.append(D)
-        ok.append(status == 0)
-    return states, Ds, torch.stack(ok), T
+        ok.append(status.cpu().numpy()[:w.n] == 0)
+    return states, Ds, np.stack(ok), T
 
 
 def dataset(sur: "Surrogate", states, Ds, T, dt, n, rows=None):
@@ -325,7 +364,11 @@ def dataset(sur: "Surrogate", states, Ds, T, dt, n, rows=None):
         Xs = sur.featurize(x0, T, Ds[s], dt, n)
         Ts = sur.targets(x0, x1, n)
         if rows is not None:
-            Xs, Ts = Xs.index_select(0, rows), Ts.index_select(0, rows)
+            xr = torch.empty((rows.shape[0], Xs.shape[1]), dtype=Xs.dtype, device=Xs.device)
+            tr = torch.empty((rows.shape[0], Ts.shape[1]), dtype=Ts.dtype, device=Ts.device)
+            adm1_gather_rows(Xs, rows, xr)
+            adm1_gather_rows(Ts, rows, tr)
+            Xs, Ts = xr, tr
         feats.append(Xs.clone())
         targs.append(Ts.clone())
     return torch.cat(feats), torch.cat(targs)
@@ -341,22 +384,14 @@ def fit_norm(sur: "Surrogate", states, Ds, T, dt, n, floor, rows=None,
     params, _ = sur.get_weights()
     sur.set_weights(params, identity_norm(floor))
     Xr, Tr = dataset(sur, states, Ds, T, dt, n, rows)
-    xf = bf16_to_float(Xr[:, :IN])
-    in_mean = xf.mean(0).double().cpu().numpy()
-    in_sd = xf.std(0).double().cpu().numpy()
+    # BF16-rounded features, as the network sees them; FP64 sums on the device
+    in_mean, in_sd = adm1_column_stats(Xr, IN, bf16=True)
     in_sd = np.where(in_sd > 1e-6, in_sd, 1.0)
-    out_mean = Tr.mean(0).double().cpu().numpy()
-    out_sd = Tr.std(0).double().cpu().numpy()
+    out_mean, out_sd = adm1_column_stats(Tr, OUT, bf16=False)
     out_sd = np.where(out_sd > 1e-8, out_sd, 1.0)
     if out_weight is not None:
         out_sd = out_sd / np.sqrt(np.asarray(out_weight, dtype=np.float64))
     return make_norm(in_mean, in_sd, out_mean, out_sd, floor)
-
-
-def bf16_to_float(Xb):
-    """BF16 bit patterns (int16 tensor) -> float32 tensor."""
-    import torch
-    return (Xb.to(torch.int32) << 16).view(torch.float32)
 
 
 def calibrate_output_bias(sur: Surrogate, X, Tg, chunk: int = 1 << 20) -> np.ndarray:
@@ -364,12 +399,7 @@ def calibrate_output_bias(sur: Surrogate, X, Tg, chunk: int = 1 << 20) -> np.nda
     (standardised units) on held-out rows (X, Tg): a coherent bias of the
     predicted increments adds up over a tank of particles and over coupling
     steps, while per-particle scatter averages out.  Returns the shift."""
-    import torch
-    acc = torch.zeros(OUT, dtype=torch.float64, device=X.device)
-    for a in range(0, X.shape[0], chunk):
-        Y = sur.forward(X[a:a + chunk])[:, :OUT]
-        acc += (Y.double() - Tg[a:a + chunk].double()).sum(dim=0)
-    shift = (acc / max(1, X.shape[0])).cpu().numpy()
+    shift, _ = adm1_surrogate_residual_stats(sur.handle, X, Tg, chunk)
     params, norm = sur.get_weights()
     params[-OUT:] -= shift.astype(np.float32)
     sur.set_weights(params, norm)
@@ -385,20 +415,22 @@ def train(sur: Surrogate, X, Tg, epochs: int, batch: int = 8192, lr: float = 1e-
     nb = n // batch
     total = max(1, epochs * nb)
     loss = torch.zeros(max(nb, 1), dtype=torch.float32, device=X.device)
-    g = torch.Generator(device=X.device)
-    g.manual_seed(seed)
+    perm = torch.empty(n, dtype=torch.int32, device=X.device)
+    xb = torch.empty((batch, X.shape[1]), dtype=X.dtype, device=X.device)
+    tb = torch.empty((batch, Tg.shape[1]), dtype=Tg.dtype, device=Tg.device)
     hist = []
     k = 0
     for e in range(epochs):
-        perm = torch.randperm(n, generator=g, device=X.device)
+        # a seeded permutation of the rows per epoch, batches gathered on the device
+        adm1_permutation(n, (seed << 32) + e, perm)
         for b in range(nb):
             idx = perm[b * batch:(b + 1) * batch]
-            xb = X.index_select(0, idx).contiguous()
-            tb = Tg.index_select(0, idx).contiguous()
+            adm1_gather_rows(X, idx, xb)
+            adm1_gather_rows(Tg, idx, tb)
             k += 1
             lr_k = 0.5 * lr * (1.0 + math.cos(math.pi * (k - 1) / total))
             sur.train_step(xb, tb, lr_k, k, loss[b:b + 1])
-        hist.append(float(loss[:nb].mean()))
+        hist.append(float(loss[:nb].cpu().numpy().astype(np.float64).mean()))
         if log:
             log(f"epoch {e}: loss {hist[-1]:.4e}")
     return hist
@@ -429,15 +461,22 @@ def train_on_transitions(ctx, sur: Surrogate, train_data: str = "field", n_trans
         states, Ds, ok, T = integrate_states(ctx, wt, train_steps)
     g = np.random.default_rng(train_seed)
     perm = g.permutation(wt.n)
-    tr = torch.from_numpy(np.sort(perm[: int(0.9 * wt.n)])).to(dev)
-    va = torch.from_numpy(np.sort(perm[int(0.9 * wt.n): int(0.95 * wt.n)])).to(dev)
+    tr_h = np.sort(perm[: int(0.9 * wt.n)]).astype(np.int32)
+    va_h = np.sort(perm[int(0.9 * wt.n): int(0.95 * wt.n)]).astype(np.int32)
+    tr, va = torch.from_numpy(tr_h).to(dev), torch.from_numpy(va_h).to(dev)
     out_weight = np.ones(OUT)
     out_weight[[8, 9, 32, 33, 34]] = gas_weight
     norm = fit_norm(sur, states, Ds, T, wt.dt, wt.n, floor, rows=tr, out_weight=out_weight)
     sur.set_weights(init_params(train_seed), norm)
     X, Tg = dataset(sur, states, Ds, T, wt.dt, wt.n, rows=tr)
-    keep = ok[:, tr].reshape(-1)
-    X, Tg = X[keep].contiguous(), Tg[keep].contiguous()
+    # transitions of clean steps only (dataset rows are step-major)
+    keep = ok[:, tr_h].reshape(-1)
+    kept = torch.from_numpy(np.flatnonzero(keep).astype(np.int32)).to(dev)
+    Xk = torch.empty((kept.shape[0], X.shape[1]), dtype=X.dtype, device=dev)
+    Tk = torch.empty((kept.shape[0], Tg.shape[1]), dtype=Tg.dtype, device=dev)
+    adm1_gather_rows(X, kept, Xk)
+    adm1_gather_rows(Tg, kept, Tk)
+    X, Tg = Xk, Tk
     Xv, Tv = dataset(sur, states, Ds, T, wt.dt, wt.n, rows=va)
     del states
     gen_s = time.perf_counter() - t0
@@ -452,7 +491,7 @@ def train_on_transitions(ctx, sur: Surrogate, train_data: str = "field", n_trans
         half = Xv.shape[0] // 2
         shift = calibrate_output_bias(sur, Xv[:half], Tv[:half])
         Xv, Tv = Xv[half:], Tv[half:]
-    val_mse = float(((sur.forward(Xv)[:, :OUT] - Tv) ** 2).mean())
+    val_mse = float(adm1_surrogate_residual_stats(sur.handle, Xv, Tv)[1].mean())
     rec = {"data": train_data, "transitions": int(keep.sum()), "particles": int(wt.n),
            "coupling_steps": train_steps, "epochs": epochs, "steps": steps,
            "seconds": train_s, "data_seconds": gen_s, "loss_first_last": [hist[0], hist[-1]],

@@ -133,3 +133,19 @@ def test_last_failures_counts_the_status(torch_cuda):
              status=torch.zeros(1, dtype=torch.uint8, device="cuda"))
     c4 = ctx.last_failures()
     assert all(v == 0 for v in c4.values())
+
+
+def test_init_refuses_non_integer_hill_exponents(torch_cuda):
+    """The kernels take the pH inhibition's power by multiplication, so a
+    parameter set whose Hill exponent 3 / (pH_UL - pH_LL) is not an integer
+    from 1 to 4 is refused at initialisation; integer ones are accepted."""
+    from paper_2311_08927_amd import adm1 as A
+    base = A.load_params()
+    for ul, ok in ((5.5, True), (5.0, True), (4.75, True), (7.0, True), (5.2, False),
+                   (4.5, False), (10.0, False)):
+        vals = dict(base, pH_UL_aa=ul)
+        if ok:
+            A.Context(64, rtol=1e-8, atol=W.atol_vector(1e-8), params=vals).close()
+        else:
+            with pytest.raises(A.ADM1Error, match="-4"):
+                A.Context(64, rtol=1e-8, atol=W.atol_vector(1e-8), params=vals)

@@ -518,7 +518,7 @@ def test_trained_network_beats_untrained(torch_cuda):
     norm = S.fit_norm(sur, states, Ds, T, w.dt, w.n, floor)
     sur.set_weights(M.init_params(4), norm)
     X, Tg = S.dataset(sur, states, Ds, T, w.dt, w.n)
-    keep = ok.reshape(-1)
+    keep = torch.from_numpy(ok.reshape(-1)).cuda()
     X, Tg = X[keep].contiguous(), Tg[keep].contiguous()
     hist = S.train(sur, X, Tg, epochs=8, batch=1024, lr=2e-3, log=print)
     assert hist[-1] < 0.1 * hist[0]
