@@ -109,16 +109,12 @@ __device__ __forceinline__ TConst load_tc(const Lds& L, int pr)
     return c;
 }
 
-// Rarely executed transcendental work (once per particle) kept out of line,
-// so that the constants of exp/log are not hoisted into the persistent loop.
-// They are called only where every lane of the wave is active: a call made
-// under a partial exec mask may overwrite the values the inactive lanes hold
-// in caller-saved registers (measured: warm-start guesses of waiting pairs
+// The starting step's root (cold starts only) kept out of line, so that the
+// constants of exp/log are not hoisted into the persistent loop.  It is
+// called only where every lane of the wave is active: a call made under a
+// partial exec mask may overwrite the values the inactive lanes hold in
+// caller-saved registers (measured: warm-start guesses of waiting pairs
 // changed, making a particle's rounding depend on its neighbours).
-__device__ __attribute__((noinline)) TConst tconst_ool(const DevParams* p, double T)
-{
-    return tconst(*p, T);
-}
 __device__ __attribute__((noinline)) double fifth_root(double x)
 {
     return exp(0.2 * log(x));
@@ -215,15 +211,9 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
             }
         }
         if (!__any(job != kNone)) break;
-        // the out-of-line helpers, here with every lane active: temperature
-        // constants of the particles being started, and the root of the
-        // starting-step estimate of those finishing it
-        // (the conditions are wave-uniform, so the exec mask stays full)
-        TConst cstart;
-        if (__any(job == kStart)) {
-            const DevParams& p0 = params_at(pp);
-            cstart = tconst_ool(&p0, job == kStart ? a.T[s.pid] : 300.0);
-        }
+        // the out-of-line root of the starting-step estimate, here with every
+        // lane active (the condition is wave-uniform, so the exec mask stays
+        // full)
         double root = 1.0;
         if (__any(job == kRoot)) root = fifth_root(job == kRoot ? 0.01 / dm : 1.0);
         if (job == kRoot) {
@@ -277,7 +267,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                 job = kNone;
                 run = false;
             } else {
-                c = cstart;
+                c = tconst(p, T);
                 c.arr *= phase_factor(a.phase, a.phase_kin, i);
                 if (!odd) {
                     L.tc[0][pr] = c.RT; L.tc[1][pr] = c.K_w; L.tc[2][pr] = c.K_a_co2;
