@@ -164,11 +164,13 @@ struct LinSparse1Lds {  // generated static-order sparse LU, matrix in LDS
 #undef ADM1_SPL_M
 };
 
-// One coupling interval for one particle on one lane.
+// One coupling interval for one particle on one lane.  Inlined: a call made
+// under a partial exec mask (lanes past n, lanes with invalid input) may
+// overwrite what the inactive lanes keep in caller-saved registers.
 template <typename R, typename Lin>
-__device__ static int integrate1(const DevParams& p, const TConst& c, double* y, double D,
-                                 const double* sin, double dt, double& H, double& Sh2,
-                                 double& hlast, int* cnt)
+__device__ __forceinline__ static int integrate1(const DevParams& p, const TConst& c, double* y,
+                                                 double D, const double* sin, double dt,
+                                                 double& H, double& Sh2, double& hlast, int* cnt)
 {
     Lin lin;
     double u[kR4Stages][NY];

@@ -76,3 +76,36 @@ def test_surrogate_refuses_other_models(torch_cuda):
     with pytest.raises(ValueError, match="standard"):
         S.Surrogate(ctx, 64)
     ctx.close()
+
+
+def test_variant_model_with_mixed_phases(torch_cuda):
+    """The second model's library with the mixed active / sediment / inert
+    population: FP64 parity against the oracle reading the same description
+    with the same phase factors, equal step counts."""
+    import torch
+    from paper_2311_08927_amd.adm1 import Context
+    from tests.gpu_common import DeviceWorkload, parity
+    w = W.cstr_population(300, seed=43)
+    ph = W.mixed_phases(w.n, seed=43, ld=w.ld)
+    ctx = Context(w.ld, rtol=RTOL, atol=W.atol_vector(RTOL), model=MODEL)
+    ctx.set_phase_kinetics(W.PHASE_KIN)
+    dw = DeviceWorkload(w)
+    dph = torch.from_numpy(ph).cuda()
+    orc = _orc(DESC)
+    Xo = w.X.copy()
+    Ho, hlo = np.full(w.ld, -1.0), np.full(w.ld, -1.0)
+    worst = 0.0
+    for s in range(2):
+        D = w.D_at(s)
+        dw.set_D(D)
+        ctx.step(dw.X, dw.T, dw.D, dw.fidx, dw.S_in, w.dt, n=w.n, H=dw.H, hlast=dw.hlast,
+                 status=dw.status, nsteps=dw.nsteps, phase=dph)
+        st_o, cnt_o = orc.step(Xo, w.T, D, w.fidx, w.feed, w.dt, H=Ho, hlast=hlo, n=w.n,
+                               phase=ph, phase_kin=W.PHASE_KIN)
+        torch.cuda.synchronize()
+        worst = max(worst, parity(dw.X.cpu().numpy(), Xo, w.n))
+        assert (dw.status.cpu().numpy() & 0x7F == 0).all() and (st_o & 0x7F == 0).all()
+        assert np.array_equal(dw.nsteps[0, :w.n].cpu().numpy(), cnt_o[0, :w.n])
+    ctx.close()
+    print(f"second model with phases: parity {worst:.3e}")
+    assert worst <= PARITY_TOL
