@@ -684,3 +684,24 @@ def test_euler_paper_interval_against_adaptive(seed):
         err.append((np.abs(ye - ya) / np.maximum(np.abs(ya), 1e-4 * nom)).max())
     assert err[0] < 2e-5
     assert 8.0 < err[0] / err[1] < 12.0, err
+
+
+
+def test_tolerance_proportionality():
+    """The adaptive integration's error against its own rtol-1e-12 solution
+    falls with the tolerance: near rtol at 1e-8 and about 100 times that at
+    1e-6, over two coupling intervals from perturbed states (an error
+    controller that did not steer would not show it)."""
+    nom = nominal()[0]
+    e = {}
+    for seed in range(1, 9):
+        x, feed, D, T = perturbed(seed)
+        res = {}
+        for rt in (1e-6, 1e-8, 1e-12):
+            res[rt] = _run(Oracle(PARAMS, rtol=rt, atol=1e-4 * rt * nom[DIFF]), x, T, D, feed,
+                           DT, steps=2)
+        den = np.maximum(np.abs(res[1e-12]), 1e-4 * nom)
+        for rt in (1e-6, 1e-8):
+            e[rt] = max(e.get(rt, 0.0), float(np.max(np.abs(res[rt] - res[1e-12]) / den)))
+    assert e[1e-8] < 1e-7
+    assert 20.0 < e[1e-6] / e[1e-8] < 500.0
