@@ -195,10 +195,11 @@ def cpu_baseline(w, rtol, n_sample, steps):
         orc.step(X, sub.T, sub.D_at(s), sub.fidx, sub.feed, sub.dt, H=H, hlast=hl, n=sub.n,
                  nthreads=cores)
     el = time.perf_counter() - t0
-    return {"value": sub.n * steps / el, "unit": "particle-steps/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{sub.n} particles ({nz} in the feed zone) x {steps} coupling steps "
-                      f"of the same workload, std::thread-style equal chunks, {el:.1f} s"}
+    rec = {"value": sub.n * steps / el, "unit": "particle-steps/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"{sub.n} particles ({nz} in the feed zone) x {steps} coupling steps "
+                     f"of the same workload, std::thread-style equal chunks, {el:.1f} s"}
+    return rec, idx, X[:, :sub.n]
 
 
 def main():
@@ -357,8 +358,18 @@ def main():
     if n_sample is None:
         n_sample = int(min(16384, max(1024, round(163840 / cpu_steps))))
     if n_sample > 0:
-        out["cpu_baseline"] = cpu_baseline(w, args.rtol, n_sample, cpu_steps)
+        out["cpu_baseline"], idx, Xo = cpu_baseline(w, args.rtol, n_sample, cpu_steps)
         out["detail"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+        if cpu_steps == K:
+            # the timed run's own final states against the oracle's on the
+            # sample (the parity metric of the tests)
+            xg = X[:, torch.from_numpy(idx).to(dev)].cpu().numpy()
+            nom = W.nominal()["state"][:, None]
+            rel = np.abs(xg - Xo) / np.maximum(np.abs(Xo), 1e-4 * nom)
+            out["detail"]["parity_vs_oracle_sample"] = {
+                "max_rel": float(rel.max()), "particles": int(len(idx)), "bar": 1e-6,
+                "metric": "|x_gpu - x_oracle| / max(|x_oracle|, 1e-4 x_nom) after the timed "
+                          "coupling steps"}
         out["detail"]["gpu_over_cpu_horizon"] = (f"both over coupling steps 0..{K - 1}"
                                                  if cpu_steps == K else
                                                  f"GPU {K} steps, CPU {cpu_steps} steps")
