@@ -116,7 +116,14 @@ typedef struct adm1_params {
  *     and eq. 8 solves and the linear algebra stay FP64).
  *   variant: step-kernel layout; -1 lets the library choose (the choice set
  *     by adm1_set_launch, else ADM1_VARIANT_SPARSE2); otherwise an
- *     ADM1_VARIANT_* value. */
+ *     ADM1_VARIANT_* value.
+ *   pivot_floor (>= 0, finite): growth guard of the static-order
+ *     factorisations (every variant but ADM1_VARIANT_DENSE1, which pivots):
+ *     an attempted step whose Newton matrix has a pivot smaller in magnitude
+ *     than pivot_floor times that row's diagonal entry before elimination is
+ *     rejected like a step whose error estimate fails (the step size shrinks,
+ *     which makes the matrix more diagonally dominant); 0 turns the guard
+ *     off. */
 typedef struct adm1_opts {
     double rtol;
     double atol[28];
@@ -125,6 +132,7 @@ typedef struct adm1_opts {
     int32_t newton_maxit;
     int32_t rate_precision;
     int32_t variant;
+    double pivot_floor;
 } adm1_opts;
 
 enum {

@@ -38,7 +38,7 @@ class adm1_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double * ND),
                 ("max_steps", ctypes.c_int32), ("newton_tol", ctypes.c_double),
                 ("newton_maxit", ctypes.c_int32), ("rate_precision", ctypes.c_int32),
-                ("variant", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("pivot_floor", ctypes.c_double)]
 
 
 class adm1_feed(ctypes.Structure):
@@ -155,14 +155,17 @@ def make_params(values: dict):
     return arr
 
 
+PIVOT_FLOOR = 1e-8  # default growth guard of the static-order factorisations
+
+
 def make_opts(rtol=1e-8, atol=None, max_steps=100000, newton_tol=1e-14, newton_maxit=100,
-              rate_precision=0, variant=-1) -> adm1_opts:
+              rate_precision=0, variant=-1, pivot_floor=PIVOT_FLOOR) -> adm1_opts:
     if atol is None:
         atol = np.full(ND, 1e-12)
     atol = np.asarray(atol, dtype=np.float64)
     assert atol.shape == (ND,)
     return adm1_opts(rtol, (ctypes.c_double * ND)(*atol), max_steps, newton_tol, newton_maxit,
-                     rate_precision, variant)
+                     rate_precision, variant, pivot_floor)
 
 
 def _ptr(t):
@@ -463,7 +466,8 @@ class Context:
         cur = dict(rtol=self.opts.rtol, atol=np.array(self.opts.atol),
                    max_steps=self.opts.max_steps, newton_tol=self.opts.newton_tol,
                    newton_maxit=self.opts.newton_maxit,
-                   rate_precision=self.opts.rate_precision, variant=self.opts.variant)
+                   rate_precision=self.opts.rate_precision, variant=self.opts.variant,
+                   pivot_floor=self.opts.pivot_floor)
         cur.update(kw)
         self.opts = make_opts(**cur)
         adm1_set_opts(self.handle, self.opts)

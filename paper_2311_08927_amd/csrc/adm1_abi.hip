@@ -196,7 +196,8 @@ int apply_opts(const adm1_opts& o, DevParams& d)
     if (!(o.rtol > 0.0) || !std::isfinite(o.rtol) || o.max_steps <= 0 ||
         !(o.newton_tol > 0.0) || o.newton_maxit <= 0 ||
         (o.rate_precision != 0 && o.rate_precision != 1) || o.variant < -1 ||
-        o.variant >= ADM1_VARIANT_COUNT)
+        o.variant >= ADM1_VARIANT_COUNT || !(o.pivot_floor >= 0.0) ||
+        !std::isfinite(o.pivot_floor))
         return ADM1_E_OPTS;
     for (int k = 0; k < 28; ++k)
         if (!(o.atol[k] > 0.0) || !std::isfinite(o.atol[k])) return ADM1_E_OPTS;
@@ -206,6 +207,7 @@ int apply_opts(const adm1_opts& o, DevParams& d)
     d.newton_qtol = 0.1 * std::sqrt(o.newton_tol);
     d.max_steps = o.max_steps;
     d.newton_maxit = o.newton_maxit;
+    d.pivot_floor = o.pivot_floor;
     return ADM1_OK;
 }
 

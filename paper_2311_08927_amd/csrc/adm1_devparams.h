@@ -49,6 +49,7 @@ typedef struct DevParams {
     double newton_tol;
     double newton_qtol;  // 0.1 sqrt(newton_tol): stop once a Newton correction is below it
     int max_steps, newton_maxit;
+    double pivot_floor;  // growth guard of the static-order LU (0: off)
 } DevParams;
 
 #ifdef __cplusplus

@@ -131,7 +131,7 @@ struct LinSparse1 {  // generated static-order sparse LU, named scalars
     {
         ADM1_SP_BUILD(alpha, D);
         bool ok = true;
-        ADM1_SP_FACTOR(ok);
+        ADM1_SP_FACTOR(ok, p.pivot_floor, alpha);
         return ok;
     }
     __device__ void solve(double* b) const { ADM1_SP_SOLVE(b); }
@@ -157,7 +157,7 @@ struct LinSparse1Lds {  // generated static-order sparse LU, matrix in LDS
     {
         ADM1_SPL_BUILD(alpha, D);
         bool ok = true;
-        ADM1_SPL_FACTOR(ok);
+        ADM1_SPL_FACTOR(ok, p.pivot_floor, alpha);
         return ok;
     }
     __device__ void solve(double* b) const { ADM1_SPL_SOLVE(b); }

@@ -489,7 +489,7 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
                         const DevParams& p = q;
                         ADM1_SP2_BUILD(alpha, D);
                     }
-                    ADM1_SP2_FACTOR(ok);
+                    ADM1_SP2_FACTOR(ok, q.pivot_floor, alpha);
                 }
             }
         }

@@ -449,9 +449,18 @@ def emit_sparse1():
         e = e.replace("alpha", "(alpha)").replace("(alpha + D)", "((alpha) + (D))")
         out.append(f"    m_{r}_{c} = {e}; \\")
     out.append("    (void)0")
-    out.append("#define ADM1_SP_FACTOR(ok) \\")
+    # growth guard (the static order does not pivot): every pivot at least
+    # `floor` times its row's scale, alpha = 1/(gamma h) for the
+    # differential rows, the diagonal entry before elimination for the two
+    # constraint rows
+    out.append("#define ADM1_SP_FACTOR(ok, floor, alpha) \\")
+    out.append("    const double gd_ = (alpha) * (floor); \\")
+    for k in (NV - 2, NV - 1):
+        out.append(f"    const double g_{k} = fabs(m_{k}_{k}) * (floor); \\")
     for k in order:
-        out.append(f"    iv_{k} = 1.0 / m_{k}_{k}; ok = ok && isfinite(iv_{k}); \\")
+        g = f"g_{k}" if k >= NV - 2 else "gd_"
+        out.append(f"    iv_{k} = 1.0 / m_{k}_{k}; "
+                   f"ok = ok & (isfinite(iv_{k}) & !(fabs(iv_{k}) * {g} > 1.0)); \\")
         for i in L[k]:
             out.append(f"    m_{i}_{k} *= iv_{k}; \\")
         for i in L[k]:
@@ -491,9 +500,14 @@ def emit_sparse1_lds():
         e = e.replace("alpha", "(alpha)").replace("(alpha + D)", "((alpha) + (D))")
         out.append(f"    {m(r, c)} = {e}; \\")
     out.append("    (void)0")
-    out.append("#define ADM1_SPL_FACTOR(ok) \\")
+    out.append("#define ADM1_SPL_FACTOR(ok, floor, alpha) \\")
+    out.append("    const double gd_ = (alpha) * (floor); \\")
+    for k in (NV - 2, NV - 1):
+        out.append(f"    const double g_{k} = fabs({m(k, k)}) * (floor); \\")
     for k in order:
-        out.append(f"    iv_{k} = 1.0 / {m(k, k)}; ok = ok && isfinite(iv_{k}); \\")
+        g = f"g_{k}" if k >= NV - 2 else "gd_"
+        out.append(f"    iv_{k} = 1.0 / {m(k, k)}; "
+                   f"ok = ok & (isfinite(iv_{k}) & !(fabs(iv_{k}) * {g} > 1.0)); \\")
         for i in L[k]:
             out.append(f"    {m(i, k)} *= iv_{k}; \\")
         for i in L[k]:
@@ -621,10 +635,24 @@ def emit_sparse2():
 
     counts = dict(bcast=0, fma_factor=0, fma_solve=0, sel=0)
     # factorisation
-    out.append("#define ADM1_SP2_FACTOR(ok) \\")
+    # growth guard: the pivots of the differential rows at least floor *
+    # alpha, those of the two constraint rows (the last pair, one per side)
+    # at least floor times their diagonal entries before elimination; every
+    # pivot's reciprocal reaches both lanes, so both take the same decision
+    out.append("#define ADM1_SP2_FACTOR(ok, floor, alpha) \\")
+    out.append("    const double gd_ = (alpha) * (floor); \\")
+    guard = {}
+    for k in range(NV):
+        if k >= NV - 2:
+            mk, sk = pair_of[k], side[k]
+            out.append(f"    const double g{k}_ = fabs(bc{sk}(w{mk}_{k})) * (floor); \\")
+            guard[k] = f"g{k}_"
+        else:
+            guard[k] = "gd_"
     for k in range(NV):
         mk, sk = pair_of[k], side[k]
-        out.append(f"    {{ const double iv = bc{sk}(1.0 / w{mk}_{k}); ok = ok && isfinite(iv); \\")
+        out.append(f"    {{ const double iv = bc{sk}(1.0 / w{mk}_{k}); "
+                   f"ok = ok & (isfinite(iv) & !(fabs(iv) * {guard[k]} > 1.0)); \\")
         counts["bcast"] += 1
         lpairs = []
         for m in range(len(pairs)):
