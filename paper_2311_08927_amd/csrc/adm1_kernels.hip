@@ -107,7 +107,7 @@ __device__ static double initial_step(const DevParams& p, const TConst& c, const
 __device__ __forceinline__ bool all_finite(const double* v, int n)
 {
     bool ok = true;
-    for (int i = 0; i < n; ++i) ok = ok && isfinite(v[i]);
+    for (int i = 0; i < n; ++i) ok = ok & isfinite(v[i]);
     return ok;
 }
 
@@ -234,7 +234,7 @@ __device__ __forceinline__ static int integrate1(const DevParams& p, const TCons
                 e += (u[5][i] / sc) * (u[5][i] / sc);
             }
             err = sqrt(e / NY);
-            ok = all_finite(y1, NY) && isfinite(err);
+            ok = all_finite(y1, NY) & isfinite(err);
         }
         ++n;
         const double fac = ok ? step_factor(err) : 0.2;
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(64, 1) k_step1(StepArgs a)
     } else {
         const double* sin = a.S_in + (int64_t)fi * NLIQ;
         bool fin = true;
-        for (int k = 0; k < NLIQ; ++k) fin = fin && isfinite(sin[k]);
+        for (int k = 0; k < NLIQ; ++k) fin = fin & isfinite(sin[k]);
         if (!fin) {
             st = 4;
         } else {
@@ -463,10 +463,10 @@ __global__ void __launch_bounds__(64) k_solve_ph(PhArgs a)
     bool fin = true;
     for (int k = 0; k < NY; ++k) {
         y[k] = a.state[state_row(k) * a.ld + i];
-        fin = fin && isfinite(y[k]);
+        fin = fin & isfinite(y[k]);
     }
     const double T = a.T[i];
-    fin = fin && isfinite(T) && T > 0.0;
+    fin = fin & isfinite(T) & (T > 0.0);
     double H = a.guess ? a.guess[i] : -1.0;
     int it = 0;
     int st = 4;

@@ -256,11 +256,11 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
             s.reject_prev = false;
             bool fin = isfinite(T) && T > 0.0 && isfinite(D) && fi >= 0 && fi < a.n_feed;
 #pragma unroll
-            for (int k = 0; k < NY; ++k) fin = fin && isfinite(yin[k]);
+            for (int k = 0; k < NY; ++k) fin = fin & isfinite(yin[k]);
             const double* sin = a.S_in + (int64_t)(fin ? fi : 0) * NLIQ;
             if (fin) {
 #pragma unroll
-                for (int k = 0; k < NLIQ; ++k) fin = fin && isfinite(sin[k]);
+                for (int k = 0; k < NLIQ; ++k) fin = fin & isfinite(sin[k]);
             }
             if (!fin) {
                 write_status(a, s, 4, odd);
@@ -327,7 +327,7 @@ __device__ static void service(const StepArgs& a, cparams_t pp, Lds& L, PairStat
                 }
                 bool neg = false;
 #pragma unroll
-                for (int k = 0; k < NY; ++k) neg = neg || yin[k] < 0.0;
+                for (int k = 0; k < NY; ++k) neg = neg | (yin[k] < 0.0);
                 if (neg) st |= 0x80;
             }
             write_status(a, s, st, odd);
@@ -541,12 +541,12 @@ __device__ static int attempt(const StepArgs& a, cparams_t pp, Lds& L, PairState
             const double at = odd ? p.atol[kVar1[m]] : p.atol[kVar0[m]];
             const double r = bv[m] * frcp(at + p.rtol * fmax(fabs(s.y[m]), fabs(y1[m])));
             e += r * r;
-            fin = fin && isfinite(y1[m]);
+            fin = fin & isfinite(y1[m]);
         }
         e += swp(e);
         const double fo = swp(fin ? 1.0 : 0.0);
         err = sqrt(e / NY);
-        ok = fin && fo == 1.0 && isfinite(err);
+        ok = fin & (fo == 1.0) & isfinite(err);
     }
     const double fac = ok ? step_factor(err) : 0.2;
     double hnew = hs * fac;
