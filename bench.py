@@ -349,7 +349,8 @@ def main():
                    "hbm_bytes_per_particle_step": F.BYTES_PER_PARTICLE_STEP,
                    "hbm_frac": w.n * F.BYTES_PER_PARTICLE_STEP / (sum(step_ms) / K / 1e3)
                    / PEAK_HBM,
-                   "step_ms": step_ms, "wall_s": wall,
+                   "step_ms": step_ms, "step_ms_median": float(np.median(step_ms)),
+                   "wall_s": wall,
                    "cold_interval_ms": step_ms[0],
                    "warm_interval_mean_ms": (sum(step_ms[1:]) / (K - 1)) if K > 1 else None},
     }
@@ -629,6 +630,12 @@ def field_comparison(args, n, steps, sur, ctx, log, gates=None, fair_rtols=None,
     audit = {}
     stream = torch.cuda.current_stream()
     for path in paths:
+        # one untimed warm-up replay of the path's first step, then the
+        # burned-in state again
+        X.copy_(X0); H.copy_(H0); hl.copy_(hl0)
+        mask(pos_k[0])
+        A.adm1_graph_launch(graph_of(path, 0), stream)
+        torch.cuda.synchronize()
         X.copy_(X0); H.copy_(H0); hl.copy_(hl0)
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -684,11 +691,17 @@ def field_comparison(args, n, steps, sur, ctx, log, gates=None, fair_rtols=None,
         return e_ch4, float(torch.quantile(e_ph[::stride], 0.99)), float(e_ph.max())
 
     rate = lambda p: wd.n * K / (ms[p] / 1e3)  # noqa: E731
+
+    def step_ms(p):
+        """Mean and median over the K timed replays of a path (ms)."""
+        v = np.asarray(launch_ms[p])
+        return {"mean": float(v.mean()), "median": float(np.median(v)), "n": int(v.size)}
     v64 = rate("fp64")
     sweep, fair = [], None
     for r in sorted(fair_rtols, reverse=True):
         e_ch4, p99, pmax = errors(f"fp64@{r:g}")
         row = {"rtol": r, "particle_steps_per_s": rate(f"fp64@{r:g}"),
+               "step_ms": step_ms(f"fp64@{r:g}"),
                "tank_methane_rel_err_max": float(e_ch4.max()), "ph_rel_err_p99": p99,
                "ph_rel_err_max": pmax}
         sweep.append(row)
@@ -700,7 +713,7 @@ def field_comparison(args, n, steps, sur, ctx, log, gates=None, fair_rtols=None,
         v = rate(f"sur{gi}")
         fbf = (fb[f"sur{gi}"].cpu().numpy() / wd.n)
         gate_rows.append({"tol_ion": ti, "tol_closure": tc, "particle_steps_per_s": v,
-                          "speedup_vs_fp64": v / v64,
+                          "step_ms": step_ms(f"sur{gi}"), "speedup_vs_fp64": v / v64,
                           "speedup_vs_fair": None if fair is None else
                           v / fair["particle_steps_per_s"],
                           "fallback_fraction_mean": float(fbf.mean()),
@@ -714,7 +727,8 @@ def field_comparison(args, n, steps, sur, ctx, log, gates=None, fair_rtols=None,
         e_ch4, p99, pmax = errors(path)
         v = rate(path)
         resync_rows.append({"period": R, "tol_ion": gates[0][0], "tol_closure": gates[0][1],
-                            "particle_steps_per_s": v, "speedup_vs_fp64": v / v64,
+                            "particle_steps_per_s": v, "step_ms": step_ms(path),
+                            "speedup_vs_fp64": v / v64,
                             "speedup_vs_fair": None if fair is None else
                             v / fair["particle_steps_per_s"],
                             "tank_methane_rel_err_max": float(e_ch4.max()),
@@ -747,6 +761,7 @@ def field_comparison(args, n, steps, sur, ctx, log, gates=None, fair_rtols=None,
                     f"captured in a HIP graph",
         "particles": wd.n, "coupling_steps": K,
         "fp64": {"rtol": 1e-8, "particle_steps_per_s": v64, "ms_per_step": ms["fp64"] / K,
+                 "step_ms": step_ms("fp64"),
                  "roofline": None if fp64_flop is None else
                  {"bound": "alu", "achieved": fp64_flop / (ms["fp64"] / 1e3) / 1e12,
                   "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
