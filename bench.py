@@ -199,7 +199,19 @@ def cpu_baseline(w, rtol, n_sample, steps):
            "kind": "oracle",
            "sample": f"{sub.n} particles ({nz} in the feed zone) x {steps} coupling steps "
                      f"of the same workload, std::thread-style equal chunks, {el:.1f} s"}
-    return rec, idx, X[:, :sub.n]
+    # the same oracle on one thread, every 32nd particle of the sample
+    one = W.subset(w, idx[::32])
+    X1 = one.X.copy()
+    H1, hl1 = np.full(one.ld, -1.0), np.full(one.ld, -1.0)
+    t1 = time.perf_counter()
+    for s in range(steps):
+        orc.step(X1, one.T, one.D_at(s), one.fidx, one.feed, one.dt, H=H1, hlast=hl1,
+                 n=one.n, nthreads=1)
+    el1 = time.perf_counter() - t1
+    single = {"value": one.n * steps / el1, "unit": "particle-steps/s", "cores": 1,
+              "sample": f"every 32nd particle of that sample ({one.n}) x {steps} coupling "
+                        f"steps, {el1:.1f} s"}
+    return rec, idx, X[:, :sub.n], single
 
 
 def main():
@@ -359,8 +371,9 @@ def main():
     if n_sample is None:
         n_sample = int(min(16384, max(1024, round(163840 / cpu_steps))))
     if n_sample > 0:
-        out["cpu_baseline"], idx, Xo = cpu_baseline(w, args.rtol, n_sample, cpu_steps)
+        out["cpu_baseline"], idx, Xo, single = cpu_baseline(w, args.rtol, n_sample, cpu_steps)
         out["detail"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+        out["detail"]["cpu_single_thread"] = single
         if cpu_steps == K:
             # the timed run's own final states against the oracle's on the
             # sample (the parity metric of the tests)
