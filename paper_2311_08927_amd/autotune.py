@@ -1,8 +1,10 @@
 """Autotuner of the step kernel's launch configuration.
 
-The design space (one coupling interval of a seeded sample of the caller's
-workload per candidate, timed with HIP events on the launching stream, every
-candidate from the same start state):
+The design space (`intervals` consecutive coupling intervals of a seeded
+sample of the caller's workload per candidate, the first from a cold start
+and the others warm-started from it as a coupling loop runs them, timed
+with HIP events on the launching stream, every candidate from the same start
+state):
   * lanes per particle and placement of the Newton matrix: one lane with a
     dense pivoted LU in private memory (ADM1_VARIANT_DENSE1), one lane with
     the static sparse LU in registers (SPARSE1) or in LDS (SPARSE1_LDS), two
@@ -87,10 +89,10 @@ def save_cache(d: dict):
 
 
 def autotune(ctx: "A.Context", X, T, D, fidx, S_in, dt, n=None, tag="", repeats=2,
-             candidates=CANDIDATES, use_cache=True, log=None) -> dict:
+             candidates=CANDIDATES, use_cache=True, log=None, intervals=1) -> dict:
     """Time the candidates on (X, T, D, fidx, S_in) -- device tensors of the
-    sample -- for one coupling interval each; returns {choice, timings_ms,
-    layout}.  X is not modified."""
+    sample -- over `intervals` coupling intervals each (the cold one, then
+    warm ones); returns {choice, timings_ms, layout}.  X is not modified."""
     import torch
     n = X.shape[1] if n is None else n
     arch = torch.cuda.get_device_properties(X.device).gcnArchName
@@ -114,7 +116,8 @@ def autotune(ctx: "A.Context", X, T, D, fidx, S_in, dt, n=None, tag="", repeats=
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            ctx.step(Xw, T, D, fidx, S_in, dt, n=n, H=H, hlast=hl, stream=stream)
+            for _ in range(intervals):
+                ctx.step(Xw, T, D, fidx, S_in, dt, n=n, H=H, hlast=hl, stream=stream)
             e1.record(stream)
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
