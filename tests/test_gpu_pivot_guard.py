@@ -72,3 +72,22 @@ def test_default_floor_and_validation(torch_cuda):
     for bad in (-1.0, float("nan"), float("inf")):
         with pytest.raises(A.ADM1Error):
             A.Context(64, rtol=RTOL, atol=W.atol_vector(RTOL), pivot_floor=bad)
+
+
+def test_floor_changed_on_a_live_context(torch_cuda):
+    """adm1_set_opts updates the device copy the two-lane kernel reads: an
+    impossible floor fails every particle, the default one restores the
+    normal step on the same inputs."""
+    import torch
+    from paper_2311_08927_amd import adm1 as A
+    w = W.cstr_population(128, seed=6)
+    ctx = A.Context(w.ld, rtol=RTOL, atol=W.atol_vector(RTOL), variant=2)
+    for floor, want in ((1e300, 2), (A.PIVOT_FLOOR, 0)):
+        ctx.set_opts(pivot_floor=floor)
+        assert ctx.opts.pivot_floor == floor
+        dw = DeviceWorkload(w)
+        ctx.step(dw.X, dw.T, dw.D, dw.fidx, dw.S_in, w.dt, n=w.n, H=dw.H, hlast=dw.hlast,
+                 status=dw.status, nsteps=dw.nsteps)
+        torch.cuda.synchronize()
+        assert ((dw.status.cpu().numpy() & 0x7F) == want).all(), floor
+    ctx.close()
