@@ -88,6 +88,8 @@ const char kParamNames[] =
 // every field of adm1_params is listed once, in order
 #define ADM1_COUNT(n) +1
 static_assert(ADM1_FAIL_SLOTS == adm1::kFailSlots, "outcome counter slots");
+// per-block partial outcome counts of the last step call
+constexpr int kFailWords = adm1::kCountBlocks * adm1::kFailSlots;
 static_assert(sizeof(adm1_params) == sizeof(double) * (0 ADM1_PARAM_FIELDS(ADM1_COUNT)),
               "adm1_params field list out of sync");
 #undef ADM1_COUNT
@@ -346,8 +348,8 @@ int adm1_init(const adm1_params* p, const adm1_opts* o, int64_t n_max, adm1_ctx*
             hipSuccess ||
         hipMalloc(&c->d_order_work, order_work) != hipSuccess ||
         hipMemset(c->d_order_work, 0, order_work) != hipSuccess ||
-        hipMalloc(&c->d_fail, adm1::kFailSlots * sizeof(unsigned long long)) != hipSuccess ||
-        hipMemset(c->d_fail, 0, adm1::kFailSlots * sizeof(unsigned long long)) !=
+        hipMalloc(&c->d_fail, kFailWords * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->d_fail, 0, kFailWords * sizeof(unsigned long long)) !=
             hipSuccess ||
         hipMalloc(&c->d_phase_kin, ADM1_MAX_PHASES * sizeof(double)) != hipSuccess ||
         set_phase_table(c, nullptr, 0) != ADM1_OK ||
@@ -545,12 +547,16 @@ int adm1_step_fixed(adm1_ctx* ctx, double* state, int64_t ld, const double* temp
 int adm1_last_failures(adm1_ctx* ctx, int64_t* host_out, void* stream)
 {
     if (!ctx || !host_out) return ADM1_E_NULL;
-    unsigned long long c[adm1::kFailSlots];
+    unsigned long long c[kFailWords];
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(c, ctx->d_fail, sizeof(c), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_rc(e);
-    for (int k = 0; k < adm1::kFailSlots; ++k) host_out[k] = (int64_t)c[k];
+    for (int k = 0; k < adm1::kFailSlots; ++k) {
+        int64_t t = 0;
+        for (int b = 0; b < adm1::kCountBlocks; ++b) t += (int64_t)c[b * adm1::kFailSlots + k];
+        host_out[k] = t;
+    }
     return ADM1_OK;
 }
 

@@ -22,7 +22,7 @@ struct adm1_ctx {
     int order_mode;      // ADM1_ORDER_* of the step kernel's work queue
     int32_t* d_order;    // cost-ordered particle list [max(n_max, 1)]
     int32_t* d_order_work;  // its histogram, bucket cursors and length
-    unsigned long long* d_fail;  // outcome counters of the last step call [kFailSlots]
+    unsigned long long* d_fail;  // per-block outcome counts of the last step call [kCountBlocks][kFailSlots]
     int32_t* static_scratch;     // this device's address of the library's static scratch
     double* d_phase_kin;  // kinetic factor of each phase id [ADM1_MAX_PHASES]
 };

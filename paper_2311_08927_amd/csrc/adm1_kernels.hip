@@ -479,15 +479,11 @@ __global__ void __launch_bounds__(64) k_solve_ph(PhArgs a)
     if (a.status) a.status[i] = (uint8_t)st;
 }
 
-// Outcome counters: one pass over the status bytes, block sums in LDS, one
-// atomic per slot and block.
-__global__ void k_count_reset(unsigned long long* c)
-{
-    if (threadIdx.x < kFailSlots) c[threadIdx.x] = 0;
-}
-
+// Outcome counters: one pass over the status bytes by a fixed grid of
+// kCountBlocks blocks, block sums in LDS, each block's sums stored to its own
+// row of the partials (the host adds the rows).
 __global__ void __launch_bounds__(256) k_count_status(const uint8_t* status, int64_t n,
-                                                      unsigned long long* c)
+                                                      unsigned long long* part_out)
 {
     __shared__ unsigned int part[kFailSlots][256];
     unsigned int loc[kFailSlots] = {0, 0, 0, 0, 0, 0, 0};
@@ -510,8 +506,9 @@ __global__ void __launch_bounds__(256) k_count_status(const uint8_t* status, int
             for (int k = 0; k < kFailSlots; ++k) part[k][threadIdx.x] += part[k][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x < kFailSlots && part[threadIdx.x][0])
-        atomicAdd(&c[threadIdx.x], (unsigned long long)part[threadIdx.x][0]);
+    // every block writes all its slots on every call: no reset, no atomics
+    if (threadIdx.x < kFailSlots)
+        part_out[blockIdx.x * kFailSlots + threadIdx.x] = part[threadIdx.x][0];
 }
 
 // Total Jacobian: minus the Schur complement of the constraint block of the
@@ -674,12 +671,8 @@ hipError_t launch_solve_ph(const PhArgs& a, hipStream_t s)
 hipError_t launch_count_status(const uint8_t* status, int64_t n, unsigned long long* counts,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_count_reset, dim3(1), dim3(64), 0, s, counts);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n <= 0) return e;
-    int64_t grid = (n + 256 * 16 - 1) / (256 * 16);
-    if (grid > 1024) grid = 1024;
-    hipLaunchKernelGGL(k_count_status, dim3((unsigned)grid), dim3(256), 0, s, status, n, counts);
+    hipLaunchKernelGGL(k_count_status, dim3(kCountBlocks), dim3(256), 0, s, status,
+                       n > 0 ? n : 0, counts);
     return hipGetLastError();
 }
 
