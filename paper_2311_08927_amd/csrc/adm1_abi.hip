@@ -12,6 +12,7 @@
 #include "adm1_ctx.h"
 #include "adm1_fixed.h"
 #include "adm1_kernels.h"
+#include "adm1_count.h"
 
 using adm1::DevParams;
 

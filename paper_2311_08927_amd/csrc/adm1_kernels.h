@@ -91,9 +91,6 @@ struct PhArgs {
 // [0] particles with a nonzero status code, [1..4] codes 1..4, [5] code 0
 // with the negative-entry bit, [6] particles counted.
 constexpr int kFailSlots = 7;
-// outcome counting: this many blocks, each writing its kFailSlots partial
-// counts (the readout sums them)
-constexpr int kCountBlocks = 64;
 
 hipError_t launch_rhs(const RhsArgs& a, int rate_precision, hipStream_t s);
 hipError_t launch_solve_ph(const PhArgs& a, hipStream_t s);

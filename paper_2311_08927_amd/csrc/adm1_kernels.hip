@@ -13,6 +13,7 @@
 
 #include "adm1_fixed.h"
 #include "adm1_kernels.h"
+#include "adm1_count.h"
 #include "adm1_model.h"
 #include "adm1_rodas4.h"
 

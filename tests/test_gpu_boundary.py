@@ -135,6 +135,29 @@ def test_last_failures_counts_the_status(torch_cuda):
     assert all(v == 0 for v in c4.values())
 
 
+
+def test_last_failures_past_one_grid_pass(torch_cuda):
+    """The count runs on a fixed grid of 64 blocks of 256 threads; 40,000
+    status bytes take three passes of it.  Invalid inputs planted on both
+    sides of each pass boundary and at the last index are all counted, and
+    the counts equal the host's count of the status array."""
+    w = W.cstr_population(40_000, seed=35)
+    ctx = make_ctx(w.ld)
+    dw = DeviceWorkload(w)
+    bad = [0, 16_383, 16_384, 16_385, 32_767, 32_768, 39_999]
+    for i in bad[::2]:
+        dw.X[4, i] = float("nan")
+    for i in bad[1::2]:
+        dw.T[i] = -1.0
+    st = ctx.step_fixed(dw.X, dw.T, dw.D, dw.fidx, dw.S_in, 0.5 / 86400.0, 10,
+                        n=w.n).cpu().numpy()
+    c = ctx.last_failures()
+    code = st & 0x7F
+    assert c["counted"] == w.n
+    assert sorted(np.nonzero(code)[0].tolist()) == bad
+    assert c["failed"] == c["nonfinite"] == int((code == 4).sum()) == len(bad)
+    assert c["negative"] == int(((code == 0) & ((st & 0x80) != 0)).sum())
+
 def test_init_refuses_non_integer_hill_exponents(torch_cuda):
     """The kernels take the pH inhibition's power by multiplication, so a
     parameter set whose Hill exponent 3 / (pH_UL - pH_LL) is not an integer
