@@ -37,12 +37,18 @@ STEP_SOURCES = ["adm1_step_sparse2.hip", "adm1_model.h", "adm1_jac_sparse2.inc",
                 "adm1_partials.inc", "adm1_stoich.inc", "adm1_devparams.h", "adm1_rodas4.h",
                 "adm1_kernels.h"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_sparse2_batched_2e20.md")
+# the same for the fixed-step kernels (whose source file holds the other
+# one-lane kernels too: any change there drops the measured figure)
+FIXED_SOURCES = ["adm1_kernels.hip", "adm1_fixed.h", "adm1_model.h", "adm1_partials.inc",
+                 "adm1_stoich.inc", "adm1_devparams.h", "adm1_kernels.h", "adm1_count.h",
+                 "adm1_rodas4.h"]
+FIXED_PROFILE = os.path.join(ROOT, "profiles", "k_fixed_cstr_110929.md")
 
 
-def step_source_hash() -> str:
+def step_source_hash(sources=None) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in STEP_SOURCES:
+    for f in STEP_SOURCES if sources is None else sources:
         with open(os.path.join(ROOT, "paper_2311_08927_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -67,6 +73,38 @@ def measured_traffic(K: int, launch: str):
     if K > len(per):
         return None
     return sum(per[:K]) / K
+
+
+def fixed_traffic(shape: str):
+    """Calibrated HBM bytes per launch of the fixed-step kernel for `shape`
+    (method|particles|substeps|interval), from the committed counter summary;
+    None when its sources changed since the counters were taken or the
+    summary covers another shape."""
+    try:
+        text = open(FIXED_PROFILE).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^- (\w+): `([^`]*)`", text, flags=re.M))
+    if kv.get("kernel_source_sha256") != step_source_hash(FIXED_SOURCES) or \
+            kv.get("shape") != shape:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib: int, dev) -> None:
+    """One device-to-device copy of `mib` MiB: the known-size kernel whose
+    byte counters calibrate those of the kernels around it."""
+    import torch
+    if mib <= 0:
+        return
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def parse():
@@ -285,12 +323,7 @@ def main():
     H.fill_(-1.0)
     hl.fill_(-1.0)
     nsteps.zero_()
-    if args.copy_probe_mib > 0:
-        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_probe(args.copy_probe_mib, dev)
     torch.cuda.synchronize()
 
     ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
@@ -491,6 +524,7 @@ def fixed_main(args):
     torch.cuda.synchronize()
     X.copy_(X0)
     H.fill_(-1.0)
+    copy_probe(args.copy_probe_mib, dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(K)]
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -510,6 +544,9 @@ def fixed_main(args):
     achieved = flop / (sum(launch_ms) / 1e3)
     value = w.n * K / (total_ms / 1e3)
     st = status.cpu().numpy()
+    traffic = None
+    if args.rate_precision == 0:
+        traffic = fixed_traffic(f"{args.method}|{w.n}|{args.substeps}|{args.interval_s:g}")
     out = {
         "metric": "ADM1 particle-steps/sec (FP64 integrator vs gated surrogate) at stated error",
         "value": value,
@@ -526,7 +563,7 @@ def fixed_main(args):
                    "path": "fixed-step explicit scheme", "method": args.method,
                    "substeps": args.substeps, "interval_s": args.interval_s},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic,
                      "kernel": f"k_fixed ({args.method})",
                      "avg_launch_ms": sum(launch_ms) / K, "flops_per_launch": flop / K},
         "detail": {"substeps_per_s": value * args.substeps,
