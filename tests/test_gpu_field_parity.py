@@ -1,5 +1,5 @@
 """FP64 parity on the lab-digester field (sec. 3.2, Table 2 case): the
-coupling loop of sec. 2.3 as the driver runs it on the GPU (inlet feed mask,
+coupling loop of sec. 2.3 as the coupling driver runs it on the GPU (inlet feed mask,
 adaptive step with warm starts, advection between intervals), and a seeded
 sample of particles, inlet ones included, recomputed by the oracle with the
 feed each of them received in each interval.  Also one cold interval of the
