@@ -4,8 +4,9 @@
 
 namespace adm1 {
 
-// blocks of k_count_status; block b stores its kFailSlots sums in row b of
-// the context's partials, which the readout adds up
-constexpr int kCountBlocks = 64;
+// blocks of k_count_status (one per compute unit of the MI355X); block b
+// stores its kFailSlots sums in row b of the context's partials, which the
+// readout adds up
+constexpr int kCountBlocks = 256;
 
 }  // namespace adm1

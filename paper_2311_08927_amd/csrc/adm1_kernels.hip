@@ -482,23 +482,38 @@ __global__ void __launch_bounds__(64) k_solve_ph(PhArgs a)
 
 // Outcome counters: one pass over the status bytes by a fixed grid of
 // kCountBlocks blocks, block sums in LDS, each block's sums stored to its own
-// row of the partials (the host adds the rows).
+// row of the partials (the host adds the rows).  A thread takes 16
+// consecutive bytes per pass as 16 independent loads, so each wave keeps
+// 1 KB in flight; the ragged end is read byte by byte.
+__device__ __forceinline__ void tally_status(unsigned v, unsigned int (&loc)[kFailSlots])
+{
+    const unsigned code = v & 0x7Fu;
+    loc[0] += code != 0;
+    loc[1] += code == 1;
+    loc[2] += code == 2;
+    loc[3] += code == 3;
+    loc[4] += code == 4;
+    loc[5] += (code == 0) & ((v & 0x80u) != 0);
+    loc[6] += 1;
+}
+
 __global__ void __launch_bounds__(256) k_count_status(const uint8_t* status, int64_t n,
                                                       unsigned long long* part_out)
 {
     __shared__ unsigned int part[kFailSlots][256];
     unsigned int loc[kFailSlots] = {0, 0, 0, 0, 0, 0, 0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const unsigned v = status[i];
-        const unsigned code = v & 0x7Fu;
-        loc[0] += code != 0;
-        loc[1] += code == 1;
-        loc[2] += code == 2;
-        loc[3] += code == 3;
-        loc[4] += code == 4;
-        loc[5] += code == 0 && (v & 0x80u);
-        loc[6] += 1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 16;
+    for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16; i0 < n;
+         i0 += stride) {
+        if (i0 + 16 <= n) {
+            unsigned v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = status[i0 + j];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) tally_status(v[j], loc);
+        } else {
+            for (int64_t i = i0; i < n; ++i) tally_status(status[i], loc);
+        }
     }
     for (int k = 0; k < kFailSlots; ++k) part[k][threadIdx.x] = loc[k];
     __syncthreads();

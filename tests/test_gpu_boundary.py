@@ -137,14 +137,18 @@ def test_last_failures_counts_the_status(torch_cuda):
 
 
 def test_last_failures_past_one_grid_pass(torch_cuda):
-    """The count runs on a fixed grid of 64 blocks of 256 threads; 40,000
-    status bytes take three passes of it.  Invalid inputs planted on both
-    sides of each pass boundary and at the last index are all counted, and
-    the counts equal the host's count of the status array."""
-    w = W.cstr_population(40_000, seed=35)
+    """The count runs on a fixed grid of 256 blocks of 256 threads, each
+    thread taking 16 consecutive status bytes per pass: one pass covers
+    2^20 bytes.  With 2^20 + 53 particles the first threads take a second
+    pass and the last 5 bytes are a ragged end read byte by byte.  Invalid
+    inputs planted on both sides of a 16-byte group, of the pass boundary
+    and in the ragged end are all counted, and the counts equal the host's
+    count of the status array."""
+    n = (1 << 20) + 53
+    w = W.cstr_population(n, seed=35)
     ctx = make_ctx(w.ld)
     dw = DeviceWorkload(w)
-    bad = [0, 16_383, 16_384, 16_385, 32_767, 32_768, 39_999]
+    bad = [0, 15, 16, (1 << 20) - 1, 1 << 20, (1 << 20) + 1, n - 5, n - 1]
     for i in bad[::2]:
         dw.X[4, i] = float("nan")
     for i in bad[1::2]:
@@ -157,6 +161,7 @@ def test_last_failures_past_one_grid_pass(torch_cuda):
     assert sorted(np.nonzero(code)[0].tolist()) == bad
     assert c["failed"] == c["nonfinite"] == int((code == 4).sum()) == len(bad)
     assert c["negative"] == int(((code == 0) & ((st & 0x80) != 0)).sum())
+
 
 def test_init_refuses_non_integer_hill_exponents(torch_cuda):
     """The kernels take the pH inhibition's power by multiplication, so a
